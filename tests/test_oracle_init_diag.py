@@ -1,0 +1,96 @@
+"""Pins of the oracle's initial state and diagnostics.
+
+* Sharp-interface limit of the three-layer state: each layer is the
+  exponential hydrostatic profile of Sec. I (eq. seteq) and pressure is
+  continuous at the interfaces (the pressure-matching condition).  With the
+  interfaces halfway between rows the trapezoid rule is exact, so the oracle
+  must reproduce that closed form to rounding.
+* The init's renormalised fields are the prescribed (rho_0, 0, T_0).
+* The tent-map mixing length of Sec. IV on a linear ramp over W rows is W/2.
+"""
+import numpy as np
+
+from oracle import lattice as L
+from oracle import lbm
+from paper_1405_1253_amd import workload as W
+
+
+def _desc(width=4.0, t=(1.05, 1.0, 0.95), k=None, phase=None):
+    if k is None:
+        k = np.tile(np.arange(1, 17), (2, 1))
+    if phase is None:
+        phase = np.zeros((2, 16))
+    return lbm.RT3(t[0], t[1], t[2], width, k, phase)
+
+
+def test_init_sharp_limit_closed_form():
+    lx, lz, g = 4, 48, 2e-3
+    Td, Tm, Tu = 1.05, 1.0, 0.95
+    _, _, _, r = L.lattice()
+    p = lbm.Params(lx, lz, 0.7, g)
+    f0, ghost = lbm.init_rt3(p, _desc(width=1e-3), np.zeros((2, 16)))
+    rho, uH, TH = lbm.hydro_fields(f0, p)
+    # paper's piecewise form, z in length units (one row = r), continuous p
+    z = r * (np.arange(lz) + 0.5)
+    z1, z2 = r * lz / 3, r * 2 * lz / 3
+    p1 = np.exp(-g * z1 / Td)                   # pressure at the lower interface
+    p2 = p1 * np.exp(-g * (z2 - z1) / Tm)       # ... at the upper interface
+    pres = np.where(z < z1, np.exp(-g * z / Td),
+                    np.where(z < z2, p1 * np.exp(-g * (z - z1) / Tm),
+                             p2 * np.exp(-g * (z - z2) / Tu)))
+    T = np.where(z < z1, Td, np.where(z < z2, Tm, Tu))
+    want = pres / T
+    want /= want.mean()
+    assert np.allclose(TH, T[None, :], rtol=1e-14, atol=0)
+    assert np.allclose(rho, want[None, :], rtol=1e-13, atol=0)
+    # density increases upward across both interfaces (unstable stack)
+    assert rho[0, lz // 3] > rho[0, lz // 3 - 1] and rho[0, 2 * lz // 3] > rho[0, 2 * lz // 3 - 1]
+
+
+def test_init_fields_are_prescribed():
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    p = lbm.Params(wl.lx, wl.lz, wl.tau, wl.g)
+    desc = lbm.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
+    f0, ghost = lbm.init_rt3(p, desc, m.amp)
+    rho, uH, TH = lbm.hydro_fields(f0, p)
+    assert np.abs(uH).max() < 1e-15
+    assert TH.min() > wl.t_u - 1e-12 and TH.max() < wl.t_d + 1e-12
+    # unperturbed state has mean density 1
+    f00, _ = lbm.init_rt3(p, desc, np.zeros((2, 16)))
+    assert abs(lbm.hydro_fields(f00, p)[0].mean() - 1) < 1e-14
+    # the lower interface T = (T_d + T_m)/2 sits at h0(x) = Lz/3 + eta(x)
+    h0, _ = lbm.interface_heights(wl.lx, wl.lz, desc, m.amp)
+    mid = 0.5 * (wl.t_d + wl.t_m)
+    for x in range(0, wl.lx, 17):
+        col = TH[x, : wl.lz // 2]
+        k = np.nonzero(col < mid)[0][0]
+        # site k has its centre at k + 1/2; interpolate between k - 1 and k
+        zc = (k - 0.5) + (col[k - 1] - mid) / (col[k - 1] - col[k])
+        assert abs(zc - h0[x]) < 0.05
+    # ghost rows equal the unperturbed state continued past the walls
+    E, _, _, _ = L.lattice()
+    gr, gu, gT = lbm.hydro_fields(ghost.transpose(2, 0, 1), p)
+    assert np.abs(gu).max() < 1e-15
+    assert np.allclose(gT[0], wl.t_d, rtol=1e-15) and np.allclose(gT[1], wl.t_u, rtol=1e-15)
+
+
+def test_tent_map_mixing_length():
+    Tu, Tm, Td = 0.95, 1.0, 1.05
+    for Wd in (10, 40, 101):
+        tb = np.concatenate([np.full(50, Td), np.linspace(Td, Tm, Wd), np.full(30, Tm),
+                             np.linspace(Tm, Tu, Wd), np.full(50, Tu)])
+        Lu, Ld = lbm.mixing_lengths(tb, Tu, Tm, Td)
+        # Wd points span Wd - 1 rows; the integral of the tent over (0, 1) is 1/2
+        assert abs(Lu - (Wd - 1) / 2) <= 0.1 and abs(Ld - (Wd - 1) / 2) <= 0.1
+    sharp = np.concatenate([np.full(50, Td), np.full(50, Tm), np.full(50, Tu)])
+    assert lbm.mixing_lengths(sharp, Tu, Tm, Td) == (0.0, 0.0)
+
+
+def test_global_sums_consistent_with_moments():
+    f = W.random_populations(3, 5, 6)
+    rho, u, T = lbm.moments(f)
+    s = lbm.global_sums(f)
+    assert np.isclose(s[0], rho.sum(), rtol=1e-14)
+    assert np.allclose(s[1:3], (rho[..., None] * u).sum((0, 1)), rtol=1e-13)
+    assert np.isclose(s[3], 0.5 * (rho * ((u ** 2).sum(-1) + 2 * T)).sum(), rtol=1e-13)
