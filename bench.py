@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Throughput of the fused D2Q37 step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pass of the whole hot path (pull streaming, wall rows,
+force-shifted BGK collide) over the lattice, in the fused kernel, with the
+populations already resident in HBM.  The default workload is the FP64
+three-layer Rayleigh-Taylor lattice of one GPU's production share,
+4096 x 12288 sites.  Prints one JSON line with MLUPS, the HBM roofline of the
+step kernel (algorithmic bytes / kernel time, timed with HIP events on the
+stream the kernel runs on) and the CPU oracle timed on a bounded sample.
+The same lattice in FP32 deviation storage is timed as a secondary figure.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D2Q37 MLUPS (fwd FP64 vs FP32) + % HBM roofline; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+Q = 37
+STEP_SRC = os.path.join(ROOT, "paper_1405_1253_amd", "csrc", "step.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def bytes_per_site(precision):
+    return 2 * Q * (8 if precision == "f64" else 4)      # 37 reads + 37 writes
+
+
+def step_source_hash():
+    h = hashlib.sha256()
+    for name in ("step.hip", "common.h", "lattice_constants.h"):
+        with open(os.path.join(ROOT, "paper_1405_1253_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(PROFILES, f"step_{precision}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"kernel_source_sha:\s*(\w+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_src or not m_b or m_src.group(1) != step_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def time_steps(lat, steps, warmup):
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(wl, columns=16, steps=8):
+    """The oracle on a strip of the same workload: `columns` full-height
+    columns of the lattice, periodic across the strip, `steps` steps."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import lbm as O
+    from paper_1405_1253_amd.workload import draw_modes
+    m = draw_modes(wl.seed)
+    p_full = O.Params(wl.lx, wl.lz, wl.tau, wl.g)
+    desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
+    f, ghost = O.init_rt3(p_full, desc, m.amp, columns=np.arange(columns))
+    p = O.Params(columns, wl.lz, wl.tau, wl.g)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.run(f, ghost, p, steps)
+        dt = time.perf_counter() - t0
+    return {"value": columns * wl.lz * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} steps of a {columns} x {wl.lz} column strip of the {wl.name} "
+                      f"lattice (numpy FP64 oracle, 1 thread, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="rt3_4096x12288")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU x-slab "
+              "decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1405_1253_amd import abi
+    from paper_1405_1253_amd.runtime import Lattice
+    from paper_1405_1253_amd.workload import WORKLOADS
+
+    abi.load()
+    wl = WORKLOADS[args.workload]
+    lat = Lattice.from_workload(wl)
+    secs, wall = time_steps(lat, args.steps, args.warmup)
+    lat.sums()                                       # raises on a diverged state
+    sites = wl.lx * wl.lz
+    ms = secs / args.steps * 1e3
+    mlups = sites * args.steps / secs / 1e6
+    bpl = bytes_per_site(wl.precision) * sites
+    achieved = bpl / (secs / args.steps) / 1e9
+    traffic = measured_traffic(wl.name, wl.precision)
+    del lat
+    torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if wl.precision == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "lx": wl.lx, "lz": wl.lz, "sites": sites,
+                   "precision": wl.precision, "tau": wl.tau, "g": wl.g},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_launch": bpl,
+                     "kernel": "lbm::step_kernel", "wall_s": round(wall, 3)},
+    }
+    if not args.no_secondary and wl.precision == "f64":
+        wl32 = WORKLOADS.get(wl.name + "_f32")
+        if wl32 is not None:
+            lat = Lattice.from_workload(wl32)
+            s32, _ = time_steps(lat, args.steps, args.warmup)
+            lat.sums()
+            del lat
+            torch.cuda.empty_cache()
+            a32 = bytes_per_site("f32dev") * sites / (s32 / args.steps) / 1e9
+            out["secondary"] = {"f32dev_mlups": round(sites * args.steps / s32 / 1e6, 1),
+                                "f32dev_ms_per_step": round(s32 / args.steps * 1e3, 4),
+                                "f32dev_hbm_gbs": round(a32, 1),
+                                "f32dev_frac": round(a32 / HBM_PEAK_GBS, 4)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * lbm.h -- C interface of the MI355X D2Q37 thermal lattice Boltzmann library.
+ *
+ * Method: Ripesi, Biferale, Schifano, Tripiccione, "Evolution of a
+ * double-front Rayleigh-Taylor system using a GPU-based high resolution
+ * thermal Lattice-Boltzmann model", Phys. Rev. E 89, 043022 (2014).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every entry point
+ * ---------------------------------------------------------------------------
+ * Lattice.  Lx x Lz sites, periodic in x, bounded by walls below row 0 and
+ * above row Lz-1 (Sec. I; Sec. III.B).  Time step 1, reference temperature 1,
+ * d = D = 2.  Gravity is the vector (0, -g), g >= 0 (Sec. II).
+ *
+ * Velocities.  37 integer displacements e_l reaching at most 3 sites; the
+ * velocity used in moments and equilibrium is xi_l = r e_l with the lattice
+ * constant r = 1.19697977039307... (caption of Fig. 2).  Population order:
+ *    l = 0            (0,0)
+ *    l = 1..4         (1,0) (-1,0) (0,1) (0,-1)
+ *    l = 5..8         (1,1) (-1,-1) (1,-1) (-1,1)
+ *    l = 9..12        (2,0) (-2,0) (0,2) (0,-2)
+ *    l = 13..20       (2,1) (-2,-1) (2,-1) (-2,1) (1,2) (-1,-2) (1,-2) (-1,2)
+ *    l = 21..24       (2,2) (-2,-2) (2,-2) (-2,2)
+ *    l = 25..28       (3,0) (-3,0) (0,3) (0,-3)
+ *    l = 29..36       (3,1) (-3,-1) (3,-1) (-3,1) (1,3) (-1,-3) (1,-3) (-1,3)
+ * i.e. the rest velocity, then shell by shell, each +e followed by -e.
+ *
+ * Layout.  A population buffer is structure-of-arrays [37][Lx][Lz], z
+ * fastest (Sec. III.B).  Element type by precision:
+ *    LBM_F64      double, the population f_l itself;
+ *    LBM_F32_DEV  float, the deviation f_l - w_l from the rest state of unit
+ *                 density (w_l = quadrature weight).
+ * Field buffers ([4][Lx][Lz], [Lz]) are always double.
+ *
+ * State.  Buffers hold post-collision populations f*.  A step reads one
+ * buffer and writes the other (the paper's prv/nxt pair, Sec. III.B).
+ *
+ * Wall table.  ghost [2][3][37] (element type of the state): ghost[0][i] is
+ * the constant population set of the virtual row -1-i below the bottom wall,
+ * ghost[1][i] that of row Lz+i above the top wall.  A pull whose source row
+ * lies outside [0, Lz) reads this table (the paper's bc step on rows 0..2 and
+ * Lz-3..Lz-1, Sec. III.B).
+ *
+ * Memory and streams.  Pointers marked (device) are device memory, (host)
+ * host memory.  All buffers are owned by the caller; the library allocates,
+ * frees and synchronises nothing, and keeps no mutable global state.  Every
+ * call only enqueues work on `stream` (a hipStream_t; NULL = null stream) and
+ * returns; results are ready when the stream reaches that point.
+ *
+ * Errors.  Arguments are checked before anything is enqueued; a failing call
+ * enqueues nothing.  Nothing is thrown, printed or aborted.  Device pointers
+ * must be 16-byte aligned.  Lx = 0 or Lz = 0 is an empty lattice: a valid
+ * call that does nothing.  Lx * Lz must not exceed 2^29.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1u
+#define LBM_Q 37
+#define LBM_MAX_MODES 32 /* interface modes per front accepted by lbm_init_rt3 */
+
+typedef void *lbm_stream_t; /* hipStream_t */
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* bad size, tau <= 1/2, g < 0, unknown flag/precision, NULL */
+    LBM_EALIAS = -2,     /* an output buffer overlaps an input buffer                  */
+    LBM_EALIGN = -3,     /* a device pointer is not 16-byte aligned                    */
+    LBM_EHIP = -4,       /* the HIP runtime refused a launch; see lbm_last_hip_error   */
+    LBM_ESCRATCH = -5,   /* scratch buffer missing or smaller than lbm_scratch_bytes   */
+    LBM_EVERSION = -6    /* params->abi_version != LBM_ABI_VERSION                      */
+};
+
+enum lbm_precision { LBM_F64 = 0, LBM_F32_DEV = 1 };
+
+enum lbm_flags {
+    LBM_PERIODIC_Z = 1u, /* test mode: z wraps like x, no walls, ghost unused */
+    LBM_NO_COLLIDE = 2u  /* test mode: streaming and walls only               */
+};
+
+typedef struct lbm_params {
+    uint32_t abi_version; /* LBM_ABI_VERSION                                  */
+    int32_t lx, lz;       /* lattice size                                     */
+    int32_t precision;    /* enum lbm_precision                               */
+    uint32_t flags;       /* enum lbm_flags, or 0                             */
+    uint32_t reserved;    /* 0                                                */
+    double tau;           /* BGK relaxation time, > 1/2                       */
+    double g;             /* gravity magnitude along -z, >= 0                 */
+} lbm_params;
+
+/* Three-layer Rayleigh-Taylor initial state (Sec. I, eq. seteq). */
+typedef struct lbm_rt3_desc {
+    double t_d, t_m, t_u;  /* bottom, middle, top layer temperatures; the walls
+                              are held at t_d (bottom) and t_u (top)          */
+    double width;          /* tanh half-width of both interfaces, sites, > 0  */
+    int32_t nmodes;        /* Fourier modes per interface, 0..LBM_MAX_MODES   */
+    int32_t reserved;      /* 0                                               */
+    const int32_t *k;      /* (host) [2][nmodes] integer wavenumbers          */
+    const double *phase;   /* (host) [2][nmodes] phases, radians              */
+} lbm_rt3_desc;
+
+/*
+ * lbm_init_rt3 -- three-layer hydrostatic initial state and wall table.
+ *
+ * Sec. I, eq. seteq and the pressure-matching condition; the tanh smoothing
+ * of the Fig. 1 caption.  Interface f (0 = lower, at Lz/3; 1 = upper, at
+ * 2Lz/3) sits at height
+ *     h_f(x) = h0_f + sum_j amp[f][j] cos(2 pi k[f][j] (x + 1/2) / Lx + phase[f][j])
+ * (sites; site (x, z) has centre z + 1/2), the temperature is
+ *     T = t_d + (t_m - t_d) s((z + 1/2 - h_0)/width) + (t_u - t_m) s((z + 1/2 - h_1)/width),
+ * s(y) = (1 + tanh y)/2, and each column is in hydrostatic balance
+ * d ln p/dz = -g/T (trapezoid rule, one row = r length units, integrated from
+ * three rows below the bottom wall), rho = C p / T with the single constant C
+ * that gives the unperturbed profile a mean density of 1.  The stored state
+ * is the equilibrium at velocity (0, -g/2) and temperature T - g^2/8, so that
+ * the renormalised fields (lbm_moments) are exactly (rho, 0, T).  The wall
+ * table holds the same construction on the unperturbed profile 3 rows past
+ * each wall.
+ *
+ *   amp        (device) double [2][desc->nmodes]
+ *   f_out      (device) state buffer [37][Lx][Lz], written
+ *   ghost_out  (device) wall table [2][3][37], written
+ * Errors: LBM_EINVAL (sizes, nmodes, width <= 0, NULL), LBM_EALIAS (f_out and
+ * ghost_out overlap), LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_init_rt3(const lbm_params *params, const lbm_rt3_desc *desc, const double *amp,
+                 void *f_out, void *ghost_out, lbm_stream_t stream);
+
+/*
+ * lbm_step -- one fused time step: pull streaming, walls, BGK collision.
+ *
+ * Sec. III.A eq. LBE with the force-shifted equilibrium (velocity u + g tau,
+ * temperature T + tau (1 - tau) g^2 / d) and the moment definitions; the
+ * propagate/bc/collide order of Sec. III.B.  For every site (x, z) and l:
+ *     g_l(x, z) = f_in_l((x - e_lx) mod Lx, z - e_lz)   (or the wall table)
+ *     rho, u, T = moments of g
+ *     f_out_l   = g_l - (g_l - f^eq_l)/tau
+ * with f^eq the 4th-order Hermite expansion of the Maxwellian.
+ *
+ *   ghost        (device) wall table [2][3][37]; may be NULL with LBM_PERIODIC_Z
+ *   f_in         (device) state buffer, read
+ *   f_out        (device) state buffer, written; must not overlap f_in
+ *   moments_out  (device, nullable) double [4][Lx][Lz]: rho, u_x, u_z, T of g
+ *                (the pre-collision moments of this step, not renormalised)
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_step(const lbm_params *params, const void *ghost, const void *f_in, void *f_out,
+             double *moments_out, lbm_stream_t stream);
+
+/*
+ * lbm_scratch_bytes -- size of the scratch buffer lbm_moments needs (bytes).
+ * Returns 0 for invalid params.
+ */
+size_t lbm_scratch_bytes(const lbm_params *params);
+
+/*
+ * lbm_moments -- renormalised fields and global diagnostics of a state.
+ *
+ * Sec. III.A (renormalisation u^H = u + g/2, T^H = T + g^2/(4D)) and Sec. IV
+ * (mean profile T(z) = (1/Lx) sum_x T).  A stored post-collision state has
+ * bare velocity u* = u + g and temperature T* = T of the step that made it,
+ * so u^H = u* - g/2 and T^H = T* + g^2/8.
+ *
+ *   f        (device) state buffer
+ *   fields   (device, nullable) double [4][Lx][Lz]: rho, u^H_x, u^H_z, T^H
+ *   tbar     (device, nullable) double [Lz]: row means of T^H
+ *   sums     (device, nullable) double [4]: sum over sites and l of f_l,
+ *            xi_lx f_l, xi_lz f_l and |xi_l|^2 f_l / 2 (mass, momentum,
+ *            energy).  Non-finite values signal a diverged state.
+ *   scratch  (device) at least lbm_scratch_bytes(params) bytes, overwritten
+ * All reductions use a fixed order: results are bitwise reproducible.
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_moments(const lbm_params *params, const void *f, double *fields, double *tbar,
+                double *sums, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+
+/*
+ * lbm_lattice -- the library's velocity set and weights (host query).
+ *   r  (host, nullable) lattice constant
+ *   w  (host, nullable) double [37] weights
+ *   e  (host, nullable) int32 [37][2] integer displacements (e_x, e_z)
+ */
+int lbm_lattice(double *r, double *w, int32_t *e);
+
+/* Static description of a status code. */
+const char *lbm_strerror(int status);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *lbm_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

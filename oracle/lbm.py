@@ -155,7 +155,7 @@ def collide(f, p):
     rho, u, T = moments(f)
     ueq, Teq = shifted_state(u, T, p)
     feq = equilibrium(rho, ueq, Teq)
-    return f - (f - feq) / p.tau
+    return np.ascontiguousarray(f - (f - feq) / p.tau)
 
 
 def step(f, ghost, p):
@@ -246,11 +246,12 @@ class RT3:
     phase: np.ndarray   # [2, nmodes]
 
 
-def interface_heights(lx, lz, desc, amp):
+def interface_heights(lx, lz, desc, amp, columns=None):
     """Heights (site units, z = 0 at the bottom wall) of the two interfaces
     h_f(x) = h0_f + sum_j amp[f, j] cos(2 pi k[f, j] (x + 1/2) / Lx + phase[f, j]),
-    with h0 = Lz/3 (lower, T_d | T_m) and 2 Lz/3 (upper, T_m | T_u)."""
-    xc = np.arange(lx) + 0.5
+    with h0 = Lz/3 (lower, T_d | T_m) and 2 Lz/3 (upper, T_m | T_u), at every
+    column or at the given column indices."""
+    xc = (np.arange(lx) if columns is None else np.asarray(columns)) + 0.5
     base = (lz / 3.0, 2.0 * lz / 3.0)
     hs = []
     for fr in range(2):
@@ -277,8 +278,11 @@ def hydrostatic_log_pressure(T, r, g):
     return np.concatenate([lp0, np.cumsum(dlp, axis=-1)], axis=-1)
 
 
-def init_rt3(p, desc, amp):
+def init_rt3(p, desc, amp, columns=None):
     """Initial post-collision state f*_0 [37, Lx, Lz] and wall table ghost.
+
+    With ``columns`` (indices into 0..Lx-1) only those columns are built:
+    f*_0 is then [37, len(columns), Lz] (columns are independent).
 
     Each column holds the three-layer temperature profile integrated in
     hydrostatic balance from three rows below the bottom wall; the density is
@@ -298,7 +302,7 @@ def init_rt3(p, desc, amp):
     C = 1.0 / rho_hs[3:3 + lz].mean()
     rho_hs = C * rho_hs
     # perturbed columns
-    h0, h1 = interface_heights(lx, lz, desc, amp)
+    h0, h1 = interface_heights(lx, lz, desc, amp, columns)
     T = layer_temperature(zc_all[None, :], h0[:, None], h1[:, None], desc)
     lp = hydrostatic_log_pressure(T, r, p.g)
     rho = C * np.exp(lp) / T

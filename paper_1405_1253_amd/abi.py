@@ -1,0 +1,149 @@
+"""ctypes binding of liblbm.so: the C entry points under the same names.
+
+Argument marshalling only -- every step of the method runs in the library's
+HIP kernels.  Buffers are torch tensors (device memory) or raw integer
+addresses; streams default to torch's current stream.  A failing call raises
+LbmError with the library's status text.  Loading fails loudly when the
+library has not been built: there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+ABI_VERSION = 1
+Q = 37
+MAX_MODES = 32
+F64, F32_DEV = 0, 1
+PERIODIC_Z, NO_COLLIDE = 1, 2
+
+STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EALIAS", -3: "LBM_EALIGN",
+          -4: "LBM_EHIP", -5: "LBM_ESCRATCH", -6: "LBM_EVERSION"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load()
+        text = lib.lbm_strerror(status).decode()
+        hip = lib.lbm_last_hip_error().decode() if status == -4 else ""
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({text}){' ' + hip if hip else ''}")
+        self.status = status
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("lx", ctypes.c_int32), ("lz", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("tau", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+class lbm_rt3_desc(ctypes.Structure):
+    _fields_ = [("t_d", ctypes.c_double), ("t_m", ctypes.c_double), ("t_u", ctypes.c_double),
+                ("width", ctypes.c_double), ("nmodes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("k", ctypes.POINTER(ctypes.c_int32)),
+                ("phase", ctypes.POINTER(ctypes.c_double))]
+
+
+_LIB = None
+_VP = ctypes.c_void_p
+
+
+def load():
+    """Load liblbm.so (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1405_1253_amd.build` (no CPU fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        lib.lbm_init_rt3.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP]
+        lib.lbm_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
+        lib.lbm_moments.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+        lib.lbm_scratch_bytes.argtypes = [P(lbm_params)]
+        lib.lbm_scratch_bytes.restype = ctypes.c_size_t
+        lib.lbm_lattice.argtypes = [P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
+        lib.lbm_strerror.argtypes = [ctypes.c_int]
+        lib.lbm_strerror.restype = ctypes.c_char_p
+        lib.lbm_last_hip_error.argtypes = []
+        lib.lbm_last_hip_error.restype = ctypes.c_char_p
+        for name in ("lbm_init_rt3", "lbm_step", "lbm_moments", "lbm_lattice"):
+            getattr(lib, name).restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def make_params(lx, lz, tau, g, precision=F64, flags=0):
+    return lbm_params(ABI_VERSION, lx, lz, precision, flags, 0, tau, g)
+
+
+def _ptr(x):
+    """Device address of a contiguous GPU tensor (or a raw integer address)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if not x.is_cuda:
+        raise ValueError("liblbm buffers must be GPU tensors")
+    if not x.is_contiguous():
+        raise ValueError("liblbm buffers must be contiguous (layout [37][Lx][Lz], z fastest)")
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(status, where):
+    if status != 0:
+        raise LbmError(status, where)
+
+
+def lbm_init_rt3(params, t_d, t_m, t_u, width, k, phase, amp, f_out, ghost_out, stream=None):
+    """Three-layer hydrostatic initial state (see include/lbm.h).
+
+    k, phase: host arrays [2, nmodes]; amp: device float64 [2, nmodes]."""
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    phase = np.ascontiguousarray(phase, dtype=np.float64)
+    nmodes = k.shape[1] if k.ndim == 2 else 0
+    desc = lbm_rt3_desc(t_d, t_m, t_u, width, nmodes, 0,
+                        k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                        phase.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    st = load().lbm_init_rt3(ctypes.byref(params), ctypes.byref(desc), _ptr(amp), _ptr(f_out),
+                             _ptr(ghost_out), _stream(stream))
+    _check(st, "lbm_init_rt3")
+
+
+def lbm_step(params, ghost, f_in, f_out, moments_out=None, stream=None):
+    """One fused propagate + bc + collide step (see include/lbm.h)."""
+    st = load().lbm_step(ctypes.byref(params), _ptr(ghost), _ptr(f_in), _ptr(f_out),
+                         _ptr(moments_out), _stream(stream))
+    _check(st, "lbm_step")
+
+
+def lbm_scratch_bytes(params):
+    return int(load().lbm_scratch_bytes(ctypes.byref(params)))
+
+
+def lbm_moments(params, f, fields=None, tbar=None, sums=None, scratch=None, stream=None):
+    """Renormalised fields, mean profile and global sums (see include/lbm.h)."""
+    nbytes = 0 if scratch is None else scratch.numel() * scratch.element_size()
+    st = load().lbm_moments(ctypes.byref(params), _ptr(f), _ptr(fields), _ptr(tbar), _ptr(sums),
+                            _ptr(scratch), nbytes, _stream(stream))
+    _check(st, "lbm_moments")
+
+
+def lbm_lattice():
+    """(r, w [37], e [37, 2]) as compiled into the library."""
+    r = ctypes.c_double()
+    w = (ctypes.c_double * Q)()
+    e = (ctypes.c_int32 * (2 * Q))()
+    _check(load().lbm_lattice(ctypes.byref(r), w, e), "lbm_lattice")
+    return r.value, np.array(w[:]), np.array(e[:], dtype=np.int64).reshape(Q, 2)

@@ -1,0 +1,219 @@
+// C ABI of the D2Q37 library: argument validation, host-side set-up and
+// dispatch to the kernels.  No allocation, no synchronisation, no global
+// mutable state except the per-thread text of the last HIP error.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return LBM_OK;
+    g_last_hip_error = hipGetErrorString(e);
+    return LBM_EHIP;
+}
+
+constexpr long long MAX_SITES = 1LL << 29;
+
+int elt_size(int precision) { return precision == LBM_F64 ? 8 : 4; }
+
+// Common parameter checks.  Sets *empty when the lattice has no sites.
+int check_params(const lbm_params *p, bool *empty) {
+    if (!p) return LBM_EINVAL;
+    if (p->abi_version != LBM_ABI_VERSION) return LBM_EVERSION;
+    if (p->lx < 0 || p->lz < 0) return LBM_EINVAL;
+    if ((long long)p->lx * (long long)p->lz > MAX_SITES) return LBM_EINVAL;
+    if (p->precision != LBM_F64 && p->precision != LBM_F32_DEV) return LBM_EINVAL;
+    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE)) return LBM_EINVAL;
+    if (p->reserved != 0) return LBM_EINVAL;
+    if (!(p->tau > 0.5) || !isfinite(p->tau)) return LBM_EINVAL;
+    if (!(p->g >= 0.0) || !isfinite(p->g)) return LBM_EINVAL;
+    *empty = (p->lx == 0 || p->lz == 0);
+    return LBM_OK;
+}
+
+bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    if (!a || !b || na == 0 || nb == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+size_t state_bytes(const lbm_params *p) {
+    return (size_t)LBM_Q * (size_t)p->lx * (size_t)p->lz * (size_t)elt_size(p->precision);
+}
+size_t ghost_bytes(const lbm_params *p) { return (size_t)2 * 3 * LBM_Q * elt_size(p->precision); }
+size_t field_bytes(const lbm_params *p) { return (size_t)4 * p->lx * p->lz * sizeof(double); }
+
+}  // namespace
+
+extern "C" {
+
+const char *lbm_strerror(int status) {
+    switch (status) {
+        case LBM_OK: return "success";
+        case LBM_EINVAL: return "invalid argument";
+        case LBM_EALIAS: return "output buffer overlaps an input buffer";
+        case LBM_EALIGN: return "device pointer is not suitably aligned";
+        case LBM_EHIP: return "HIP runtime error";
+        case LBM_ESCRATCH: return "scratch buffer missing or too small";
+        case LBM_EVERSION: return "lbm_params.abi_version does not match the library";
+        default: return "unknown status";
+    }
+}
+
+const char *lbm_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+int lbm_lattice(double *r, double *w, int32_t *e) {
+    if (r) *r = lbm::R;
+    for (int l = 0; l < LBM_Q; ++l) {
+        if (w) w[l] = lbm::W[l];
+        if (e) {
+            e[2 * l] = lbm::EX[l];
+            e[2 * l + 1] = lbm::EZ[l];
+        }
+    }
+    return LBM_OK;
+}
+
+size_t lbm_scratch_bytes(const lbm_params *p) {
+    bool empty = false;
+    if (check_params(p, &empty) != LBM_OK || empty) return 0;
+    return lbm::moments_scratch_bytes(p->lx, p->lz);
+}
+
+int lbm_step(const lbm_params *p, const void *ghost, const void *f_in, void *f_out,
+             double *moments_out, lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!f_in || !f_out) return LBM_EINVAL;
+    if (!ghost && !(p->flags & LBM_PERIODIC_Z)) return LBM_EINVAL;
+    if (!aligned(f_in, 16) || !aligned(f_out, 16) || !aligned(ghost, 8) || !aligned(moments_out, 8))
+        return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const size_t sb = state_bytes(p);
+    if (overlap(f_in, sb, f_out, sb) || overlap(ghost, ghost_bytes(p), f_out, sb) ||
+        overlap(moments_out, field_bytes(p), f_in, sb) ||
+        overlap(moments_out, field_bytes(p), f_out, sb) ||
+        overlap(moments_out, field_bytes(p), ghost, ghost_bytes(p)))
+        return LBM_EALIAS;
+    lbm::StepArgs a;
+    a.f_in = f_in;
+    a.f_out = f_out;
+    a.ghost = ghost;
+    a.mom = moments_out;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.tau = p->tau;
+    a.omega = 1.0 / p->tau;
+    a.g = p->g;
+    a.flags = p->flags;
+    return hip_status(lbm::launch_step(a, p->precision, (hipStream_t)stream));
+}
+
+int lbm_moments(const lbm_params *p, const void *f, double *fields, double *tbar, double *sums,
+                void *scratch, size_t scratch_bytes, lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!f) return LBM_EINVAL;
+    if (!aligned(f, 16) || !aligned(fields, 8) || !aligned(tbar, 8) || !aligned(sums, 8) ||
+        !aligned(scratch, 256))
+        return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const bool need_scratch = tbar || sums;
+    if (need_scratch && (!scratch || scratch_bytes < lbm::moments_scratch_bytes(p->lx, p->lz)))
+        return LBM_ESCRATCH;
+    const size_t sb = state_bytes(p), fb = field_bytes(p);
+    const size_t tb = (size_t)p->lz * sizeof(double), scb = need_scratch ? scratch_bytes : 0;
+    if (overlap(fields, fb, f, sb) || overlap(tbar, tb, f, sb) || overlap(sums, 32, f, sb) ||
+        overlap(scratch, scb, f, sb) || overlap(fields, fb, tbar, tb) || overlap(fields, fb, sums, 32) ||
+        overlap(tbar, tb, sums, 32) || overlap(scratch, scb, fields, fb) ||
+        overlap(scratch, scb, tbar, tb) || overlap(scratch, scb, sums, 32))
+        return LBM_EALIAS;
+    if (!fields && !tbar && !sums) return LBM_OK;
+    lbm::MomentArgs a;
+    a.f = f;
+    a.fields = fields;
+    a.tbar = tbar;
+    a.sums = sums;
+    a.scratch = scratch;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.g = p->g;
+    return hip_status(lbm::launch_moments(a, p->precision, (hipStream_t)stream));
+}
+
+int lbm_init_rt3(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, void *f_out,
+                 void *ghost_out, lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!d || !f_out || !ghost_out) return LBM_EINVAL;
+    if (d->nmodes < 0 || d->nmodes > LBM_MAX_MODES || d->reserved != 0) return LBM_EINVAL;
+    if (d->nmodes > 0 && (!d->k || !d->phase || !amp)) return LBM_EINVAL;
+    if (!(d->width > 0.0) || !isfinite(d->width)) return LBM_EINVAL;
+    if (!(d->t_d > 0.0) || !(d->t_m > 0.0) || !(d->t_u > 0.0) || !isfinite(d->t_d) ||
+        !isfinite(d->t_m) || !isfinite(d->t_u))
+        return LBM_EINVAL;
+    for (int i = 0; i < 2 * d->nmodes; ++i)
+        if (!isfinite(d->phase[i])) return LBM_EINVAL;
+    if (!aligned(f_out, 16) || !aligned(ghost_out, 8) || !aligned(amp, 8)) return LBM_EALIGN;
+    if (overlap(f_out, state_bytes(p), ghost_out, ghost_bytes(p))) return LBM_EALIAS;
+    if (empty) return LBM_OK;
+
+    lbm::InitArgs a;
+    memset(&a, 0, sizeof(a));
+    a.f_out = f_out;
+    a.ghost_out = ghost_out;
+    a.amp = amp;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.nmodes = d->nmodes;
+    a.g = p->g;
+    a.t_d = d->t_d;
+    a.t_m = d->t_m;
+    a.t_u = d->t_u;
+    a.width = d->width;
+    for (int f = 0; f < 2; ++f)
+        for (int j = 0; j < d->nmodes; ++j) {
+            a.k[f][j] = d->k[f * d->nmodes + j];
+            a.phase[f][j] = d->phase[f * d->nmodes + j];
+        }
+
+    // Unperturbed column, rows -3 .. Lz+2, on the host: the density
+    // normalisation and the wall rows.  Same construction as the columns:
+    // trapezoid rule for d ln p/dz = -g/T, one row = r length units.
+    const int lz = p->lz, n = lz + 6;
+    std::vector<double> T(n), lnp(n);
+    for (int i = 0; i < n; ++i) {
+        const double zc = (double)(i - 3) + 0.5;
+        const double s0 = 0.5 * (1.0 + tanh((zc - lz / 3.0) / d->width));
+        const double s1 = 0.5 * (1.0 + tanh((zc - 2.0 * lz / 3.0) / d->width));
+        T[i] = d->t_d + (d->t_m - d->t_d) * s0 + (d->t_u - d->t_m) * s1;
+    }
+    lnp[0] = 0.0;
+    for (int i = 1; i < n; ++i) lnp[i] = lnp[i - 1] - p->g * lbm::R * 0.5 * (1.0 / T[i - 1] + 1.0 / T[i]);
+    double mean = 0.0;
+    for (int i = 3; i < 3 + lz; ++i) mean += exp(lnp[i]) / T[i];
+    mean /= (double)lz;
+    a.norm = 1.0 / mean;
+    const int rows[6] = {2, 1, 0, 3 + lz, 4 + lz, 5 + lz};   // -1,-2,-3, Lz,Lz+1,Lz+2
+    for (int i = 0; i < 6; ++i) {
+        a.ghost_t[i] = T[rows[i]];
+        a.ghost_rho[i] = a.norm * exp(lnp[rows[i]]) / T[rows[i]];
+    }
+    return hip_status(lbm::launch_init(a, p->precision, (hipStream_t)stream));
+}
+
+}  // extern "C"

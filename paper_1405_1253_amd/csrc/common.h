@@ -1,0 +1,83 @@
+// Device-side building blocks shared by the D2Q37 kernels.
+//
+// Equilibrium (Sec. III.A): the 4th-order Hermite expansion of the Maxwellian
+// about the unit-temperature Gaussian, f^eq_l = w_l rho P(x_l), with
+// x_l = xi_l . v, u2 = |v|^2, th = T - 1 and xi2 = |xi_l|^2.  Collecting the
+// expansion in powers of x gives, for every velocity of one shell,
+//     P(+-x) = (A0 + A2 x^2 + x^4/24) +- x (A1 + x^2/6)
+//     A2 = 1/2 - u2/4 + th (xi2 - 6)/4
+//     A1 = 1 - u2/2 + th (xi2 - 4)/2
+//     A0 = 1 - u2/2 + th (xi2 - 2)/2 + u2^2/8 + th u2 (4 - xi2)/4
+//          + th^2 (xi2^2 - 8 xi2 + 8)/8
+// so the three shell coefficients are computed once per shell and each +-e
+// pair costs one even and one odd polynomial.  The kernels evaluate this
+// factored form; the equivalent tensor contraction costs ~10x more flops and
+// would make the FP64 step compute-bound on this chip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice_constants.h"
+
+namespace lbm {
+
+constexpr int BLOCK = 256;   // threads per block, one site each along z
+constexpr double D = 2.0;    // space dimension
+
+// Shell coefficients of the factored equilibrium.  A0m1 = A0 - 1 so that the
+// FP32 deviation form never forms 1 + small.
+template <typename R>
+struct ShellCoef {
+    R a0m1, a1, a2;
+};
+
+template <typename R>
+__device__ __forceinline__ ShellCoef<R> shell_coef(R u2, R th, R xi2) {
+    ShellCoef<R> c;
+    c.a2 = R(0.5) - R(0.25) * u2 + R(0.25) * th * (xi2 - R(6));
+    c.a1 = R(1) - R(0.5) * u2 + R(0.5) * th * (xi2 - R(4));
+    c.a0m1 = -R(0.5) * u2 + R(0.5) * th * (xi2 - R(2)) + R(0.125) * u2 * u2
+             + R(0.25) * th * u2 * (R(4) - xi2)
+             + R(0.125) * th * th * (xi2 * xi2 - R(8) * xi2 + R(8));
+    return c;
+}
+
+// Even and odd parts of P - 1 at projection x for one shell.
+template <typename R>
+__device__ __forceinline__ void pair_poly(const ShellCoef<R> &c, R x, R &even_m1, R &odd) {
+    const R x2 = x * x;
+    even_m1 = c.a0m1 + x2 * (c.a2 + x2 * R(1.0 / 24.0));
+    odd = x * (c.a1 + x2 * R(1.0 / 6.0));
+}
+
+// Full FP64 equilibrium f^eq_l(rho, v, T) for all 37 populations (used by
+// the initial state and the wall table, not by the step's hot loop).
+__device__ __forceinline__ void equilibrium_f64(double rho, double vx, double vz, double T,
+                                                double feq[Q]) {
+    const double u2 = vx * vx + vz * vz, th = T - 1.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const ShellCoef<double> c = shell_coef<double>(u2, th, XI2_SHELL[SHELL[l]]);
+        double ev, od;
+        pair_poly<double>(c, R * (EX[l] * vx + EZ[l] * vz), ev, od);
+        feq[l] = W[l] * rho * (1.0 + ev + od);
+    }
+}
+
+// Wrap an index into [0, n) for any integer (periodic directions).
+__device__ __forceinline__ int wrap(int i, int n) {
+    int m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+// Map the hardware block index onto a logical tile index so that each XCD
+// (blocks are dealt round-robin over 8 XCDs) gets a contiguous range of
+// tiles: neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
+    const uint32_t nx = 8, q = nblocks / nx, rem = nblocks % nx;
+    const uint32_t j = b % nx, i = b / nx;
+    return (j < rem ? j * (q + 1) : rem * (q + 1) + (j - rem) * q) + i;
+}
+
+}  // namespace lbm

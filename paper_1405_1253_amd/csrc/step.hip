@@ -1,0 +1,189 @@
+// Fused D2Q37 time step: pull streaming + wall rows + force-shifted BGK collide.
+//
+// Sec. III.A eq. LBE and the shifted equilibrium; Sec. III.B step order
+// (propagate, bc, collide) and the prv/nxt pair of lattice copies.
+//
+// Mapping.  One thread per site; a block is 256 consecutive sites of one
+// column (z fastest), so every population access of a wavefront is a
+// contiguous 512-byte (FP64) or 256-byte (FP32) run.  The pull source of
+// population l is column (x - e_lx) mod Lx, rows z - e_lz: the column offset
+// is uniform over the block (scalar), the row shift is an immediate offset.
+// Each input element is read by exactly one site, so the step moves
+// 37 reads + 37 writes per site and is bound by HBM bandwidth; the arithmetic
+// (~500 flops per site with the factored equilibrium) stays well under the
+// FP64 ridge.
+//
+// Walls.  Blocks within 3 rows of either wall (or of a ragged end) take a
+// second, block-uniform code path that substitutes the wall table for
+// sources outside [0, Lz) or wraps z in the periodic test mode; all other
+// blocks run the branch-free path.
+#include "common.h"
+#include "kernels.h"
+
+namespace lbm {
+
+template <int PREC>
+struct Elt;
+template <>
+struct Elt<P_F64> {
+    using T = double;
+};
+template <>
+struct Elt<P_F32_DEV> {
+    using T = float;
+};
+
+template <int PREC, bool EDGE>
+__device__ __forceinline__ void step_tile(const StepArgs &a, int x, int z0) {
+    using E = typename Elt<PREC>::T;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    const E *__restrict__ fin = static_cast<const E *>(a.f_in);
+    E *__restrict__ fout = static_cast<E *>(a.f_out);
+    const E *__restrict__ ghost = static_cast<const E *>(a.ghost);
+    const int z = z0 + (int)threadIdx.x;
+    const bool active = !EDGE || z < a.lz;
+    const int zq = (EDGE && z >= a.lz) ? a.lz - 1 : z;   // idle lanes read a valid row
+
+    // ---- propagate + bc: gather the 37 incoming populations -------------
+    E v[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const int xs = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
+        const E *src = fin + (size_t)l * N + (size_t)xs * (size_t)a.lz;
+        if (!EDGE) {
+            v[l] = src[z - EZ[l]];
+        } else {
+            const int zs = zq - EZ[l];
+            if (a.flags & F_PERIODIC_Z)
+                v[l] = src[wrap(zs, a.lz)];
+            else if (zs < 0)
+                v[l] = ghost[(-zs - 1) * Q + l];
+            else if (zs >= a.lz)
+                v[l] = ghost[(3 + zs - a.lz) * Q + l];
+            else
+                v[l] = src[zs];
+        }
+    }
+
+    const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
+    if (a.flags & F_NO_COLLIDE) {
+        if (active) {
+#pragma unroll
+            for (int l = 0; l < Q; ++l) fout[(size_t)l * N + site] = v[l];
+        }
+        return;
+    }
+
+    // ---- moments (FP64 in both precisions) -------------------------------
+    double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const double f = (double)v[l];
+        s0 += f;
+        if (EX[l] != 0) sx += EX[l] * f;
+        if (EZ[l] != 0) sz += EZ[l] * f;
+        if (SHELL[l] != 0) s2 += (EX[l] * EX[l] + EZ[l] * EZ[l]) * f;
+    }
+    // FP32 deviations d_l = f_l - w_l: sum w = 1, sum w xi = 0, sum w xi^2 = D
+    const double rho = (PREC == P_F64) ? s0 : 1.0 + s0;
+    const double inv = 1.0 / rho;
+    const double ux = R * sx * inv, uz = R * sz * inv;
+    const double e2 = (PREC == P_F64) ? R2 * s2 : D + R2 * s2;
+    const double T = (e2 * inv - ux * ux - uz * uz) / D;
+
+    if (a.mom && active) {
+        a.mom[site] = rho;
+        a.mom[N + site] = ux;
+        a.mom[2 * N + site] = uz;
+        a.mom[3 * N + site] = T;
+    }
+
+    // ---- force-shifted equilibrium and BGK relaxation --------------------
+    // equilibrium arguments: v = u + tau g_vec, th = T + tau (1 - tau) g^2 / D - 1
+    const double vx = ux, vz = uz - a.tau * a.g;
+    const double th = T + a.tau * (1.0 - a.tau) * a.g * a.g / D - 1.0;
+    const double u2 = vx * vx + vz * vz;
+
+    if (PREC == P_F64) {
+        const double om = a.omega, keep = 1.0 - a.omega;
+#pragma unroll
+        for (int s = 0; s < NSHELL; ++s) {
+            const ShellCoef<double> c = shell_coef<double>(u2, th, XI2_SHELL[s]);
+            const double wr = W_SHELL[s] * rho;
+#pragma unroll
+            for (int l = 0; l < Q; ++l) {
+                if (SHELL[l] != s) continue;
+                if (l == 0) {
+                    const double feq = wr * (1.0 + c.a0m1);
+                    if (active) __builtin_nontemporal_store(keep * (double)v[0] + om * feq, &fout[site]);
+                    continue;
+                }
+                if ((l & 1) == 0) continue;   // handled with its +e partner l-1
+                double ev, od;
+                pair_poly<double>(c, R * (EX[l] * vx + EZ[l] * vz), ev, od);
+                const double even = wr * (1.0 + ev), odd = wr * od;
+                const double fp = keep * (double)v[l] + om * (even + odd);
+                const double fm = keep * (double)v[l + 1] + om * (even - odd);
+                if (active) {
+                    __builtin_nontemporal_store(fp, &fout[(size_t)l * N + site]);
+                    __builtin_nontemporal_store(fm, &fout[(size_t)(l + 1) * N + site]);
+                }
+            }
+        }
+    } else {
+        // deviation form: d^eq_l = w_l (rho P_l - 1) = w_l (drho + rho (P_l - 1))
+        const float drho = (float)s0, rhof = (float)rho;
+        const float u2f = (float)u2, thf = (float)th;
+        const float vxf = (float)vx, vzf = (float)vz;
+        const float om = (float)a.omega;
+#pragma unroll
+        for (int s = 0; s < NSHELL; ++s) {
+            const ShellCoef<float> c = shell_coef<float>(u2f, thf, (float)XI2_SHELL[s]);
+            const float w = (float)W_SHELL[s];
+#pragma unroll
+            for (int l = 0; l < Q; ++l) {
+                if (SHELL[l] != s) continue;
+                if (l == 0) {
+                    const float deq = w * (drho + rhof * c.a0m1);
+                    if (active) __builtin_nontemporal_store(v[0] + om * (deq - v[0]), &fout[site]);
+                    continue;
+                }
+                if ((l & 1) == 0) continue;
+                float ev, od;
+                pair_poly<float>(c, (float)R * ((float)EX[l] * vxf + (float)EZ[l] * vzf), ev, od);
+                const float dp = w * (drho + rhof * (ev + od));
+                const float dm = w * (drho + rhof * (ev - od));
+                const float op = v[l] + om * (dp - v[l]);
+                const float omn = v[l + 1] + om * (dm - v[l + 1]);
+                if (active) {
+                    __builtin_nontemporal_store(op, &fout[(size_t)l * N + site]);
+                    __builtin_nontemporal_store(omn, &fout[(size_t)(l + 1) * N + site]);
+                }
+            }
+        }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void step_kernel(StepArgs a, int nzb, uint32_t nblocks) {
+    const uint32_t t = xcd_tile(blockIdx.x, nblocks);
+    const int x = (int)(t / (uint32_t)nzb);
+    const int z0 = (int)(t % (uint32_t)nzb) * BLOCK;
+    const bool edge = (z0 < 3) || (z0 + BLOCK + 3 > a.lz);
+    if (edge)
+        step_tile<PREC, true>(a, x, z0);
+    else
+        step_tile<PREC, false>(a, x, z0);
+}
+
+hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s) {
+    const int nzb = (a.lz + BLOCK - 1) / BLOCK;
+    const uint32_t nblocks = (uint32_t)nzb * (uint32_t)a.lx;
+    if (precision == P_F64)
+        hipLaunchKernelGGL(step_kernel<P_F64>, dim3(nblocks), dim3(BLOCK), 0, s, a, nzb, nblocks);
+    else
+        hipLaunchKernelGGL(step_kernel<P_F32_DEV>, dim3(nblocks), dim3(BLOCK), 0, s, a, nzb, nblocks);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

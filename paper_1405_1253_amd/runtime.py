@@ -1,0 +1,94 @@
+"""Lattice: device buffers and stream plumbing around the C entry points.
+
+Owns the prv/nxt pair of population buffers (Sec. III.B), the wall table and
+the diagnostics scratch, all as torch tensors on one GPU; every computation is
+a call into liblbm.so on the current torch stream.
+"""
+import numpy as np
+import torch
+
+from . import abi
+from .workload import Workload, draw_modes
+
+
+class Lattice:
+    def __init__(self, lx, lz, tau, g, precision="f64", flags=0, device="cuda"):
+        if precision not in ("f64", "f32dev"):
+            raise ValueError(precision)
+        self.lx, self.lz, self.tau, self.g = lx, lz, tau, g
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.params = abi.make_params(lx, lz, tau, g,
+                                      abi.F64 if precision == "f64" else abi.F32_DEV, flags)
+        self.device = torch.device(device)
+        self.buf = [torch.empty((abi.Q, lx, lz), dtype=self.dtype, device=self.device)
+                    for _ in range(2)]
+        self.cur = 0
+        self.ghost = torch.zeros((2, 3, abi.Q), dtype=self.dtype, device=self.device)
+        nbytes = max(abi.lbm_scratch_bytes(self.params), 256)
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.steps_done = 0
+
+    # ---- construction -----------------------------------------------------
+    @classmethod
+    def from_workload(cls, wl: Workload, modes=None, amp=None, device="cuda", **kw):
+        lat = cls(wl.lx, wl.lz, wl.tau, wl.g, precision=wl.precision, device=device, **kw)
+        modes = modes if modes is not None else draw_modes(wl.seed)
+        a = modes.amp if amp is None else amp
+        lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k, modes.phase, a)
+        return lat
+
+    def init_rt3(self, t_d, t_m, t_u, width, k, phase, amp):
+        if not torch.is_tensor(amp):
+            amp = torch.as_tensor(np.asarray(amp, dtype=np.float64), device=self.device)
+        amp = amp.to(device=self.device, dtype=torch.float64).contiguous()
+        abi.lbm_init_rt3(self.params, t_d, t_m, t_u, width, k, phase, amp,
+                         self.buf[0], self.ghost)
+        self.cur = 0
+        self.steps_done = 0
+        self._amp = amp   # keep alive until the stream has consumed it
+
+    # ---- time stepping ----------------------------------------------------
+    @property
+    def state(self):
+        return self.buf[self.cur]
+
+    def set_state(self, f):
+        self.buf[self.cur].copy_(f)
+
+    def step(self, n=1, moments_out=None):
+        """Advance n steps; moments_out (optional) receives the last step's
+        pre-collision moments [4, lx, lz]."""
+        for i in range(n):
+            mo = moments_out if i == n - 1 else None
+            abi.lbm_step(self.params, self.ghost, self.buf[self.cur], self.buf[1 - self.cur], mo)
+            self.cur = 1 - self.cur
+        self.steps_done += n
+
+    # ---- diagnostics ------------------------------------------------------
+    def fields(self):
+        out = torch.empty((4, self.lx, self.lz), dtype=torch.float64, device=self.device)
+        abi.lbm_moments(self.params, self.state, fields=out, scratch=self.scratch)
+        return out
+
+    def tbar(self):
+        out = torch.empty(self.lz, dtype=torch.float64, device=self.device)
+        abi.lbm_moments(self.params, self.state, tbar=out, scratch=self.scratch)
+        return out
+
+    def sums(self, check=True):
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        abi.lbm_moments(self.params, self.state, sums=out, scratch=self.scratch)
+        if check:
+            host = out.cpu()
+            if not torch.isfinite(host).all():
+                raise FloatingPointError(f"non-finite global sums {host.tolist()}: state diverged")
+        return out
+
+    def populations(self):
+        """Full populations f_l as float64 (adds the weights back in FP32 mode)."""
+        f = self.state.to(torch.float64)
+        if self.precision == "f32dev":
+            _, w, _ = abi.lbm_lattice()
+            f = f + torch.as_tensor(w, device=self.device)[:, None, None]
+        return f

@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every entry point include/lbm.h declares, its compiled constants
+agree with the oracle's independent quadrature solve, the constant header is
+reproducible from its generator, and invalid arguments are refused before
+anything is launched."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lattice as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1405_1253_amd import abi as mod
+    mod.load()
+    return mod
+
+
+def test_exports_every_declared_symbol(abi):
+    names = declared_functions()
+    assert "lbm_step" in names and "lbm_init_rt3" in names and "lbm_moments" in names
+    lib = ctypes.CDLL(abi.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_library_constants_match_oracle(abi):
+    r, w, e = abi.lbm_lattice()
+    E, _, w_o, r_o = L.lattice()
+    assert np.array_equal(e, E)                  # documented population order
+    assert abs(r - r_o) <= 1e-14
+    assert np.abs(w / w_o - 1).max() <= 1e-13
+
+
+def test_constant_header_is_generated():
+    csrc = os.path.join(ROOT, "paper_1405_1253_amd", "csrc")
+    out = subprocess.run([sys.executable, os.path.join(csrc, "gen_lattice.py")],
+                         check=True, capture_output=True, text=True).stdout
+    assert out.strip() == open(os.path.join(csrc, "lattice_constants.h")).read().strip()
+
+
+def _call_step(abi, params, ghost=1 << 20, f_in=2 << 30, f_out=4 << 30, mom=None):
+    return abi.load().lbm_step(ctypes.byref(params), ghost, f_in, f_out, mom, None)
+
+
+def test_step_rejects_bad_arguments(abi):
+    mk = abi.make_params
+    assert _call_step(abi, mk(16, 16, 0.5, 0.0)) == -1           # tau <= 1/2
+    assert _call_step(abi, mk(16, 16, 0.7, -1e-3)) == -1         # g < 0
+    assert _call_step(abi, mk(-1, 16, 0.7, 0.0)) == -1
+    assert _call_step(abi, mk(1 << 15, 1 << 15, 0.7, 0.0)) == -1  # too many sites
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, precision=7)) == -1
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=8)) == -1
+    p = mk(16, 16, 0.7, 0.0)
+    p.abi_version = 99
+    assert _call_step(abi, p) == -6
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0), ghost=None) == -1   # walls need a table
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0), f_in=None) == -1
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0), f_out=(2 << 30) + 8) == -3
+    # output overlapping the input
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0), f_out=(2 << 30) + 4096) == -2
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0), mom=(2 << 30) + 4096) == -2
+
+
+def test_empty_lattice_is_a_no_op(abi):
+    for lx, lz in ((0, 16), (16, 0)):
+        assert _call_step(abi, abi.make_params(lx, lz, 0.7, 0.0)) == 0
+        assert abi.lbm_scratch_bytes(abi.make_params(lx, lz, 0.7, 0.0)) == 0
+
+
+def test_moments_and_init_reject_bad_arguments(abi):
+    lib = abi.load()
+    p = abi.make_params(64, 64, 0.7, 1e-4)
+    need = abi.lbm_scratch_bytes(p)
+    assert need > 0
+    # sums requested with a scratch buffer that is too small
+    st = lib.lbm_moments(ctypes.byref(p), 1 << 30, None, None, 1 << 20, 3 << 30, need - 8, None)
+    assert st == -5
+    st = lib.lbm_moments(ctypes.byref(p), 1 << 30, None, None, 1 << 20, None, 0, None)
+    assert st == -5
+    k = np.ones((2, 40), np.int32)
+    ph = np.zeros((2, 40))
+    desc = abi.lbm_rt3_desc(1.05, 1.0, 0.95, 4.0, 40, 0,
+                            k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                            ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert lib.lbm_init_rt3(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 3 << 30, None) == -1
+    desc.nmodes = 16
+    desc.width = 0.0
+    assert lib.lbm_init_rt3(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 3 << 30, None) == -1
+
+
+def test_error_strings(abi):
+    lib = abi.load()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.lbm_strerror(code)

@@ -1,0 +1,92 @@
+"""FP32 deviation storage against the FP64 oracle.
+
+The FP32 form stores d_l = f_l - w_l, collides in FP32 and keeps only the
+moments (and so T) in FP64.  Error bound, per step and relative to f_l:
+the largest FP32 intermediates of the equilibrium polynomial are
+|P_l - 1| <~ 0.5 (outer shell, |T - 1| <= 0.05), so with round-off
+u = 2^-24 per operation and ~5 operations in the chain the deviation of
+d^eq is <~ 5 u * 0.5 w_l ~ 1.5e-7 w_l, the stored input adds u |d_l| and the
+relaxation another u |d_l|: <~ 3e-7 w_l, i.e. <= 5e-7 f_l (f_l >= 0.6 w_l).
+Over n steps the bound grows at most linearly: n * 3e-7; 100 steps -> 3e-5.
+The tests assert these bounds and print the per-field max and RMS errors.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbm as O
+from paper_1405_1253_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1405_1253_amd import abi as mod
+    mod.load()
+    return mod
+
+
+@pytest.fixture(scope="module")
+def traj():
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    p = O.Params(wl.lx, wl.lz, wl.tau, wl.g)
+    desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
+    f0, ghost = O.init_rt3(p, desc, m.amp)
+    f1 = O.step(f0, ghost, p)
+    f100 = O.run(f1, ghost, p, 99)
+    return wl, m, p, f0, ghost, f1, f100
+
+
+def _gpu_run(abi, wl, m, steps):
+    from paper_1405_1253_amd.runtime import Lattice
+    lat = Lattice(wl.lx, wl.lz, wl.tau, wl.g, precision="f32dev")
+    lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase, m.amp)
+    snaps = {0: lat.populations().cpu().numpy()}
+    for t in range(1, steps + 1):
+        lat.step()
+        if t in (1, steps):
+            snaps[t] = lat.populations().cpu().numpy()
+    return lat, snaps
+
+
+def test_f32_deviation_error_bounds(abi, traj):
+    wl, m, p, f0, ghost, f1, f100 = traj
+    lat, snaps = _gpu_run(abi, wl, m, 100)
+    rel = {t: float(np.max(np.abs(snaps[t] - ref) / ref)) for t, ref in ((0, f0), (1, f1), (100, f100))}
+    print("FP32-dev max rel err on f: init %.2e, 1 step %.2e, 100 steps %.2e" % (rel[0], rel[1], rel[100]))
+    assert rel[0] <= U32                  # init: one rounding of d_l, |d_l| < f_l
+    assert rel[1] <= 5e-7
+    assert rel[100] <= 3e-5
+
+
+def test_f32_field_errors(abi, traj):
+    wl, m, p, f0, ghost, f1, f100 = traj
+    lat, _ = _gpu_run(abi, wl, m, 100)
+    got = lat.fields().cpu().numpy()
+    rho, uH, TH = O.hydro_fields(f100, p)
+    ref = {"rho": rho, "u_x": uH[..., 0], "u_z": uH[..., 1], "T": TH}
+    for i, (name, r) in enumerate(ref.items()):
+        err = got[i] - r
+        print(f"FP32-dev vs FP64 oracle after 100 steps, {name}: max {np.abs(err).max():.2e} "
+              f"rms {np.sqrt(np.mean(err ** 2)):.2e}")
+    assert np.abs(got[0] / rho - 1).max() <= 3e-5
+    assert np.abs(got[3] / TH - 1).max() <= 3e-5
+    assert np.abs(got[1] - uH[..., 0]).max() <= 3e-5 and np.abs(got[2] - uH[..., 1]).max() <= 3e-5
+
+
+def test_f32_propagate_keeps_deviation_bits(abi):
+    """Streaming of deviations is a permutation: bit-exact against the oracle's
+    pull applied to the same float32 array."""
+    lx, lz = 64, 300
+    d = (W.random_populations(9, lx, lz) - 1.0).astype(np.float32) * 1e-3
+    ghost = (W.random_ghost(10) - 2.5).astype(np.float32) * 1e-3
+    params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F32_DEV, abi.NO_COLLIDE)
+    fin = torch.as_tensor(d, device=DEV)
+    fout = torch.empty_like(fin)
+    abi.lbm_step(params, torch.as_tensor(ghost, device=DEV), fin, fout)
+    want = O.pull(d, ghost, O.Params(lx, lz, 0.7, 1e-4, no_collide=True))
+    assert np.array_equal(fout.cpu().numpy(), want)
