@@ -155,7 +155,8 @@ int lbm_step(const lbm_params *params, const void *ghost, const void *f_in, void
              double *moments_out, lbm_stream_t stream);
 
 /*
- * lbm_scratch_bytes -- size of the scratch buffer lbm_moments needs (bytes).
+ * lbm_scratch_bytes -- size of the scratch buffer that lbm_moments,
+ * lbm_objective and lbm_init_rt3_vjp need (bytes).
  * Returns 0 for invalid params.
  */
 size_t lbm_scratch_bytes(const lbm_params *params);
@@ -180,6 +181,67 @@ size_t lbm_scratch_bytes(const lbm_params *params);
  */
 int lbm_moments(const lbm_params *params, const void *f, double *fields, double *tbar,
                 double *sums, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+
+/*
+ * lbm_objective -- mixing objective of a state and (optionally) its gradient.
+ *
+ * Sec. IV: mean profile T(z) of T^H, tent map Theta(b) = 2b on (0, 1/2),
+ * 2(1 - b) on [1/2, 1), 0 elsewhere, and the two mixing lengths of eq. 3L
+ * summed over rows (one row = 1):
+ *     L_u = sum_z Theta((T(z) - t_u)/(t_m - t_u)),  L_d = sum_z Theta((T(z) - t_m)/(t_d - t_m)).
+ * With KE = (1/2) sum_sites rho |u^H|^2 the objective is J = wk KE + wl (L_u + L_d).
+ *
+ *   desc      (host) only t_d > t_m > t_u are used
+ *   f         (device) state buffer
+ *   j_out     (device) double [3]: J, KE, L_u + L_d
+ *   lam_seed  (device, nullable) double [37][Lx][Lz]: dJ/df_l at every site
+ *             (the tent map's slope is taken as 2, -2, 0 on the three pieces)
+ *   scratch   (device) at least lbm_scratch_bytes(params) bytes
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void *f, double wk, double wl,
+                  double *j_out, double *lam_seed, void *scratch, size_t scratch_bytes,
+                  lbm_stream_t stream);
+
+/*
+ * lbm_adjoint_step -- transposed Jacobian of one lbm_step.
+ *
+ * Differentiates the step of Sec. III.A (pull, walls, force-shifted BGK
+ * collision) with respect to its input state: given lam_in = dJ/df_out it
+ * writes lam_out = dJ/df_in.  With m = (rho, u, T) the step's pre-collision
+ * moments at site x, omega = 1/tau and mu = omega (dF/dm)^T lam_in(x),
+ *     G_l(x) = (1 - omega) lam_in_l(x) + alpha + beta . xi_l + gamma |xi_l|^2,
+ *     lam_out_l(y) = G_l(y + e_l)  (x periodic; 0 where y + e_l is beyond a wall),
+ *     alpha = mu_rho - mu_u . u/rho + mu_T (|u|^2 - 2T)/(2 rho),
+ *     beta = mu_u/rho - mu_T u/rho,  gamma = mu_T/(2 rho).
+ * The wall table is constant and receives no derivative.
+ *
+ *   moments  (device) double [4][Lx][Lz]: rho, u_x, u_z, T written by the
+ *            forward lbm_step's moments_out (may be NULL with LBM_NO_COLLIDE)
+ *   lam_in   (device) double [37][Lx][Lz]
+ *   lam_out  (device) double [37][Lx][Lz], must not overlap lam_in or moments
+ * The adjoint is always double; params->precision only names the forward
+ * state it belongs to.
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_adjoint_step(const lbm_params *params, const double *moments, const double *lam_in,
+                     double *lam_out, lbm_stream_t stream);
+
+/*
+ * lbm_init_rt3_vjp -- gradient of lbm_init_rt3 with respect to the mode
+ * amplitudes: d_amp[f][j] = sum over sites and l of lam0_l dF0_l/damp[f][j],
+ * through the tanh profile, the column pressure integral and the
+ * equilibrium (Sec. I, eq. seteq).  The wall table does not depend on amp.
+ *
+ *   desc, amp  as passed to lbm_init_rt3
+ *   lam0       (device) double [37][Lx][Lz]: dJ/df*_0
+ *   d_amp      (device) double [2][nmodes], written
+ *   scratch    (device) at least lbm_scratch_bytes(params) bytes
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_init_rt3_vjp(const lbm_params *params, const lbm_rt3_desc *desc, const double *amp,
+                     const double *lam0, double *d_amp, void *scratch, size_t scratch_bytes,
+                     lbm_stream_t stream);
 
 /*
  * lbm_lattice -- the library's velocity set and weights (host query).

@@ -69,7 +69,13 @@ def load():
         lib.lbm_strerror.restype = ctypes.c_char_p
         lib.lbm_last_hip_error.argtypes = []
         lib.lbm_last_hip_error.restype = ctypes.c_char_p
-        for name in ("lbm_init_rt3", "lbm_step", "lbm_moments", "lbm_lattice"):
+        lib.lbm_objective.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, ctypes.c_double,
+                                      ctypes.c_double, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+        lib.lbm_adjoint_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP]
+        lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
+                                         ctypes.c_size_t, _VP]
+        for name in ("lbm_init_rt3", "lbm_step", "lbm_moments", "lbm_lattice", "lbm_objective",
+                     "lbm_adjoint_step", "lbm_init_rt3_vjp"):
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -106,17 +112,28 @@ def _check(status, where):
         raise LbmError(status, where)
 
 
-def lbm_init_rt3(params, t_d, t_m, t_u, width, k, phase, amp, f_out, ghost_out, stream=None):
+class RT3Desc:
+    """Host-side lbm_rt3_desc with the arrays it points to kept alive."""
+
+    def __init__(self, t_d, t_m, t_u, width, k=None, phase=None):
+        self.k = np.ascontiguousarray(np.zeros((2, 0)) if k is None else k, dtype=np.int32)
+        self.phase = np.ascontiguousarray(np.zeros((2, 0)) if phase is None else phase,
+                                          dtype=np.float64)
+        nmodes = self.k.shape[1] if self.k.ndim == 2 else 0
+        self.c = lbm_rt3_desc(t_d, t_m, t_u, width, nmodes, 0,
+                              self.k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                              self.phase.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    @property
+    def nmodes(self):
+        return self.c.nmodes
+
+
+def lbm_init_rt3(params, desc, amp, f_out, ghost_out, stream=None):
     """Three-layer hydrostatic initial state (see include/lbm.h).
 
-    k, phase: host arrays [2, nmodes]; amp: device float64 [2, nmodes]."""
-    k = np.ascontiguousarray(k, dtype=np.int32)
-    phase = np.ascontiguousarray(phase, dtype=np.float64)
-    nmodes = k.shape[1] if k.ndim == 2 else 0
-    desc = lbm_rt3_desc(t_d, t_m, t_u, width, nmodes, 0,
-                        k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                        phase.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-    st = load().lbm_init_rt3(ctypes.byref(params), ctypes.byref(desc), _ptr(amp), _ptr(f_out),
+    desc: RT3Desc (host k, phase [2, nmodes]); amp: device float64 [2, nmodes]."""
+    st = load().lbm_init_rt3(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(f_out),
                              _ptr(ghost_out), _stream(stream))
     _check(st, "lbm_init_rt3")
 
@@ -147,3 +164,29 @@ def lbm_lattice():
     e = (ctypes.c_int32 * (2 * Q))()
     _check(load().lbm_lattice(ctypes.byref(r), w, e), "lbm_lattice")
     return r.value, np.array(w[:]), np.array(e[:], dtype=np.int64).reshape(Q, 2)
+
+
+def _nbytes(t):
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def lbm_objective(params, desc, f, wk, wl, j_out, lam_seed=None, scratch=None, stream=None):
+    """J = wk KE + wl (L_u + L_d) into j_out[3] and optionally dJ/df (see include/lbm.h)."""
+    st = load().lbm_objective(ctypes.byref(params), ctypes.byref(desc.c), _ptr(f), wk, wl,
+                              _ptr(j_out), _ptr(lam_seed), _ptr(scratch), _nbytes(scratch),
+                              _stream(stream))
+    _check(st, "lbm_objective")
+
+
+def lbm_adjoint_step(params, moments, lam_in, lam_out, stream=None):
+    """lam_out = (d step / d f_in)^T lam_in (see include/lbm.h)."""
+    st = load().lbm_adjoint_step(ctypes.byref(params), _ptr(moments), _ptr(lam_in), _ptr(lam_out),
+                                 _stream(stream))
+    _check(st, "lbm_adjoint_step")
+
+
+def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):
+    """d_amp = (d init / d amp)^T lam0 (see include/lbm.h)."""
+    st = load().lbm_init_rt3_vjp(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(lam0),
+                                 _ptr(d_amp), _ptr(scratch), _nbytes(scratch), _stream(stream))
+    _check(st, "lbm_init_rt3_vjp")

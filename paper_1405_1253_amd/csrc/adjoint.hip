@@ -1,0 +1,467 @@
+// Reverse mode of the fused step, of the mixing objective and of the
+// three-layer initial state.
+//
+// The paper has no adjoint; these kernels differentiate the forward kernels'
+// arithmetic exactly (Sec. III.A step; Sec. IV mixing lengths; Sec. I init).
+//
+// Adjoint step (push form).  With lam_t = dJ/df*_t and m = (rho, u, T) the
+// pre-collision moments of step t at site x,
+//     G_l(x) = (1 - omega) lam_l(x) + alpha(x) + beta(x) . xi_l + gamma(x) |xi_l|^2
+// where mu = omega (dF/dm)^T lam(x) and
+//     alpha = mu_rho - mu_u . u / rho + mu_T (|u|^2 - D T) / (D rho)
+//     beta  = mu_u / rho - 2 mu_T u / (D rho),   gamma = mu_T / (D rho),
+// and lam_{t-1,l}(y) = G_l(y + e_l).  Each site computes its own G from its
+// own 37 lam values and 4 moments and writes G_l to site x - e_l: every
+// output element has exactly one writer (a permutation), so the kernel moves
+// 37 + 4 reads and 37 writes per site.  Rows y whose source y + e_l lies
+// beyond a wall receive an explicit zero (those pulls read the constant wall
+// table, which carries no derivative).
+//
+// Equilibrium derivatives.  With P(x) = A0 + A1 x + A2 x^2 + x^3/6 + x^4/24
+// (common.h), x = xi . v, u2 = |v|^2, th = T_eq - 1:
+//     dP/dv  = (A1 + 2 A2 x + x^2/2 + x^3/6) xi + 2 v dP/du2
+//     dP/du2 = dA0/du2 - x/2 - x^2/4,  dA0/du2 = -1/2 + u2/4 + th (4 - xi2)/4
+//     dP/dth = dA0/dth + x (xi2 - 4)/2 + x^2 (xi2 - 6)/4,
+//     dA0/dth = (xi2 - 2)/2 + u2 (4 - xi2)/4 + th (xi2^2 - 8 xi2 + 8)/4
+// and F_l = w_l rho P_l, so dF/drho = w P, dF/dv = w rho dP/dv, dF/dT = w rho dP/dth.
+#include <type_traits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace lbm {
+
+// sum_l lam_l w_l {P_l, dP_l/dx xi_l, dP_l/du2, dP_l/dth} at (v, th)
+struct EqVjp {
+    double sp, sxx, sxz, su2, sth;
+};
+
+__device__ __forceinline__ EqVjp eq_vjp_sums(const double lam[Q], double vx, double vz, double th) {
+    const double u2 = vx * vx + vz * vz;
+    EqVjp r = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NSHELL; ++s) {
+        const double xi2 = XI2_SHELL[s];
+        const ShellCoef<double> c = shell_coef<double>(u2, th, xi2);
+        const double a0 = 1.0 + c.a0m1;
+        const double a0_u2 = -0.5 + 0.25 * u2 + 0.25 * th * (4.0 - xi2);
+        const double a0_th = 0.5 * (xi2 - 2.0) + 0.25 * u2 * (4.0 - xi2) +
+                             0.25 * th * (xi2 * xi2 - 8.0 * xi2 + 8.0);
+        const double a1_th = 0.5 * (xi2 - 4.0), a2_th = 0.25 * (xi2 - 6.0);
+        const double w = W_SHELL[s];
+        double sp = 0.0, sxx = 0.0, sxz = 0.0, su2 = 0.0, sth = 0.0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+            if (SHELL[l] != s) continue;
+            if (l == 0) {   // rest velocity: x = 0, xi = 0
+                sp += lam[0] * a0;
+                su2 += lam[0] * a0_u2;
+                sth += lam[0] * a0_th;
+                continue;
+            }
+            if ((l & 1) == 0) continue;      // -e handled with its +e partner
+            const double cx = R * EX[l], cz = R * EZ[l];
+            const double x = cx * vx + cz * vz, x2 = x * x;
+            const double lp = lam[l] + lam[l + 1], lm = lam[l] - lam[l + 1];
+            // P(+-x) = pe +- po, P'(+-x) = de +- do_, etc.
+            const double pe = a0 + x2 * (c.a2 + x2 * (1.0 / 24.0));
+            const double po = x * (c.a1 + x2 * (1.0 / 6.0));
+            const double de = c.a1 + 0.5 * x2, dodd = x * (2.0 * c.a2 + x2 * (1.0 / 6.0));
+            sp += lp * pe + lm * po;
+            // xi_{l+1} = -xi_l: lam_l P'(x) xi_l + lam_{l+1} P'(-x) (-xi_l)
+            const double dx = lm * de + lp * dodd;
+            sxx += dx * cx;
+            sxz += dx * cz;
+            su2 += lp * (a0_u2 - 0.25 * x2) - lm * 0.5 * x;
+            sth += lp * (a0_th + a2_th * x2) + lm * a1_th * x;
+        }
+        r.sp += w * sp;
+        r.sxx += w * sxx;
+        r.sxz += w * sxz;
+        r.su2 += w * su2;
+        r.sth += w * sth;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint step
+// ---------------------------------------------------------------------------
+template <bool EDGE>
+__device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0) {
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    const int z = z0 + (int)threadIdx.x;
+    if (EDGE && z >= a.lz) return;
+    const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
+    // uniform column base + 32-bit per-lane byte offset for every access
+    const uint32_t zoff = (uint32_t)z * 8u;
+    double lam[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l)
+        lam[l] = ldg_off(a.lam_in + (size_t)l * N + (size_t)x * (size_t)a.lz, zoff);
+
+    // G_l = keep lam_l + alpha + beta . xi_l + gamma |xi_l|^2 (NO_COLLIDE: G = lam)
+    double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
+    if (!(a.flags & F_NO_COLLIDE)) {
+        const double *mcol = a.mom + (size_t)x * (size_t)a.lz;
+        const double rho = ldg_off(mcol, zoff), ux = ldg_off(mcol + N, zoff),
+                     uz = ldg_off(mcol + 2 * N, zoff), T = ldg_off(mcol + 3 * N, zoff);
+        const double vx = ux, vz = uz - a.tau * a.g;
+        const double th = T + a.tau * (1.0 - a.tau) * a.g * a.g / D - 1.0;
+        const EqVjp s = eq_vjp_sums(lam, vx, vz, th);
+        const double om = a.omega;
+        const double mu_rho = om * s.sp;
+        const double mux = om * rho * (s.sxx + 2.0 * vx * s.su2);
+        const double muz = om * rho * (s.sxz + 2.0 * vz * s.su2);
+        const double mu_t = om * rho * s.sth;
+        const double inv = 1.0 / rho, idr = 1.0 / (D * rho);
+        alpha = mu_rho - (mux * ux + muz * uz) * inv + mu_t * (ux * ux + uz * uz - D * T) * idr;
+        bx = R * (mux * inv - 2.0 * mu_t * ux * idr);
+        bz = R * (muz * inv - 2.0 * mu_t * uz * idr);
+        gamma = mu_t * idr;
+        keep = 1.0 - om;
+    }
+
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const double G = keep * lam[l] + alpha + (EX[l] * bx + EZ[l] * bz) + gamma * XI2_SHELL[SHELL[l]];
+        const int xd = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
+        const int zd = z - EZ[l];
+        double *dst = a.lam_out + (size_t)l * N + (size_t)xd * (size_t)a.lz;
+        if (!EDGE) {
+            stg_off(dst - EZ[l], zoff, G);
+        } else if (a.flags & F_PERIODIC_Z) {
+            dst[wrap(zd, a.lz)] = G;
+        } else {
+            if (zd >= 0 && zd < a.lz) dst[zd] = G;
+            // lam_out_l(z) = G_l(z + e_lz) has no writer when row z + e_lz lies
+            // beyond a wall: that pull read the constant wall table
+            const int zsrc = z + EZ[l];
+            if (zsrc < 0 || zsrc >= a.lz) a.lam_out[(size_t)l * N + site] = 0.0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void adjoint_step_kernel(AdjointArgs a, int nzb) {
+    const int x = (int)(blockIdx.x / (uint32_t)nzb);
+    const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BLOCK;
+    if ((z0 < 3) || (z0 + BLOCK + 3 > a.lz))
+        adjoint_tile<true>(a, x, z0);
+    else
+        adjoint_tile<false>(a, x, z0);
+}
+
+hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
+    const int nzb = (a.lz + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(adjoint_step_kernel, dim3((uint32_t)nzb * (uint32_t)a.lx), dim3(BLOCK), 0, s, a,
+                       nzb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// objective J = wk KE + wl (L_u + L_d) and its seed dJ/df*
+// ---------------------------------------------------------------------------
+constexpr int OXC = 64;   // columns per strip
+
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct ObjLayout {
+    int nxc, nzb, nb;
+    size_t tpart, kpart, dtbar, misc, total;   // byte offsets
+};
+
+static ObjLayout obj_layout(int lx, int lz) {
+    ObjLayout L;
+    L.nxc = (lx + OXC - 1) / OXC;
+    L.nzb = (lz + BLOCK - 1) / BLOCK;
+    L.nb = L.nxc * L.nzb;
+    L.tpart = 0;
+    L.kpart = al256((size_t)L.nxc * lz * sizeof(double));
+    L.dtbar = L.kpart + al256((size_t)L.nb * sizeof(double));
+    L.misc = L.dtbar + al256((size_t)lz * sizeof(double));
+    L.total = L.misc + 256;
+    return L;
+}
+
+size_t objective_scratch_bytes(int lx, int lz) { return obj_layout(lx, lz).total; }
+
+template <int PREC>
+__device__ __forceinline__ void site_moments(const void *fp, size_t N, size_t site, double &rho, double &ux,
+                                             double &uz, double &T) {
+    using E = typename std::conditional<PREC == P_F64, double, float>::type;
+    const E *f = static_cast<const E *>(fp);
+    double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const double v = (double)f[(size_t)l * N + site];
+        s0 += v;
+        if (EX[l] != 0) sx += EX[l] * v;
+        if (EZ[l] != 0) sz += EZ[l] * v;
+        if (SHELL[l] != 0) s2 += (EX[l] * EX[l] + EZ[l] * EZ[l]) * v;
+    }
+    rho = (PREC == P_F64) ? s0 : 1.0 + s0;
+    const double e2 = (PREC == P_F64) ? R2 * s2 : D + R2 * s2;
+    const double inv = 1.0 / rho;
+    ux = R * sx * inv;
+    uz = R * sz * inv;
+    T = (e2 * inv - ux * ux - uz * uz) / D;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void objective_pass1(ObjectiveArgs a, ObjLayout L) {
+    __shared__ double red[BLOCK];
+    char *sc = static_cast<char *>(a.scratch);
+    double *tpart = reinterpret_cast<double *>(sc + L.tpart);
+    double *kpart = reinterpret_cast<double *>(sc + L.kpart);
+    const int zb = blockIdx.x % L.nzb, xc = blockIdx.x / L.nzb;
+    const int tid = threadIdx.x, z = zb * BLOCK + tid;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    double tacc = 0.0, ke = 0.0;
+    if (z < a.lz) {
+        const int x1 = min(xc * OXC + OXC, a.lx);
+        for (int x = xc * OXC; x < x1; ++x) {
+            double rho, ux, uz, T;
+            site_moments<PREC>(a.f, N, (size_t)x * a.lz + z, rho, ux, uz, T);
+            const double uhz = uz + 0.5 * a.g;                 // u^H = u* - g_vec/2
+            tacc += T + a.g * a.g / (4.0 * D);                  // T^H
+            ke += 0.5 * rho * (ux * ux + uhz * uhz);
+        }
+        tpart[(size_t)xc * a.lz + z] = tacc;
+    }
+    red[tid] = ke;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) kpart[blockIdx.x] = red[0];
+}
+
+__device__ __forceinline__ double tent(double b) {
+    return (b > 0.0 && b < 0.5) ? 2.0 * b : ((b >= 0.5 && b < 1.0) ? 2.0 * (1.0 - b) : 0.0);
+}
+__device__ __forceinline__ double tent_slope(double b) {
+    return (b > 0.0 && b < 0.5) ? 2.0 : ((b >= 0.5 && b < 1.0) ? -2.0 : 0.0);
+}
+
+// One block: T(z), the tent sums, dJ/dT(z) and J.
+__global__ __launch_bounds__(BLOCK) void objective_pass2(ObjectiveArgs a, ObjLayout L) {
+    __shared__ double red[3][BLOCK];
+    char *sc = static_cast<char *>(a.scratch);
+    const double *tpart = reinterpret_cast<const double *>(sc + L.tpart);
+    const double *kpart = reinterpret_cast<const double *>(sc + L.kpart);
+    double *dtbar = reinterpret_cast<double *>(sc + L.dtbar);
+    const int tid = threadIdx.x;
+    double lu = 0.0, ld = 0.0, ke = 0.0;
+    for (int z = tid; z < a.lz; z += BLOCK) {
+        double s = 0.0;
+        for (int c = 0; c < L.nxc; ++c) s += tpart[(size_t)c * a.lz + z];
+        const double tb = s / (double)a.lx;
+        const double bu = (tb - a.t_u) / (a.t_m - a.t_u), bd = (tb - a.t_m) / (a.t_d - a.t_m);
+        lu += tent(bu);
+        ld += tent(bd);
+        dtbar[z] = a.wl * (tent_slope(bu) / (a.t_m - a.t_u) + tent_slope(bd) / (a.t_d - a.t_m));
+    }
+    for (int b = tid; b < L.nb; b += BLOCK) ke += kpart[b];
+    red[0][tid] = lu;
+    red[1][tid] = ld;
+    red[2][tid] = ke;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int k = 0; k < 3; ++k) red[k][tid] += red[k][tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double L_ = red[0][0] + red[1][0];
+        a.j_out[0] = a.wk * red[2][0] + a.wl * L_;
+        a.j_out[1] = red[2][0];
+        a.j_out[2] = L_;
+    }
+}
+
+// Seed lam_N = dJ/df*: dJ/drho = wk |u^H|^2/2, dJ/du* = wk rho u^H,
+// dJ/dT* = dJ/dT(z) / Lx, chained through the moment Jacobian.
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void objective_seed(ObjectiveArgs a, ObjLayout L) {
+    const double *dtbar = reinterpret_cast<const double *>(static_cast<char *>(a.scratch) + L.dtbar);
+    const int x = blockIdx.x / L.nzb, z = (blockIdx.x % L.nzb) * BLOCK + threadIdx.x;
+    if (z >= a.lz) return;
+    const size_t N = (size_t)a.lx * (size_t)a.lz, site = (size_t)x * a.lz + z;
+    double rho, ux, uz, T;
+    site_moments<PREC>(a.f, N, site, rho, ux, uz, T);
+    const double uhz = uz + 0.5 * a.g;
+    const double g_rho = 0.5 * a.wk * (ux * ux + uhz * uhz);
+    const double gux = a.wk * rho * ux, guz = a.wk * rho * uhz;
+    const double g_t = dtbar[z] / (double)a.lx;
+    const double inv = 1.0 / rho, idr = 1.0 / (D * rho);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const double cx = R * EX[l] - ux, cz = R * EZ[l] - uz;
+        a.lam_seed[(size_t)l * N + site] =
+            g_rho + (gux * cx + guz * cz) * inv + g_t * (cx * cx + cz * cz - D * T) * idr;
+    }
+}
+
+hipError_t launch_objective(const ObjectiveArgs &a, int precision, hipStream_t s) {
+    const ObjLayout L = obj_layout(a.lx, a.lz);
+    if (precision == P_F64)
+        hipLaunchKernelGGL(objective_pass1<P_F64>, dim3(L.nb), dim3(BLOCK), 0, s, a, L);
+    else
+        hipLaunchKernelGGL(objective_pass1<P_F32_DEV>, dim3(L.nb), dim3(BLOCK), 0, s, a, L);
+    hipLaunchKernelGGL(objective_pass2, dim3(1), dim3(BLOCK), 0, s, a, L);
+    if (a.lam_seed) {
+        const dim3 g((uint32_t)L.nzb * (uint32_t)a.lx);
+        if (precision == P_F64)
+            hipLaunchKernelGGL(objective_seed<P_F64>, g, dim3(BLOCK), 0, s, a, L);
+        else
+            hipLaunchKernelGGL(objective_seed<P_F32_DEV>, g, dim3(BLOCK), 0, s, a, L);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initial-state VJP: dJ/d amp from lam_0 = dJ/df*_0
+// ---------------------------------------------------------------------------
+// Per column (one block), rows i = 0 .. Lz+2 stand for rows k = i - 3.
+// Forward: T_i (tanh profile of the heights), dlp_i = -g r (1/T_{i-1} + 1/T_i)/2,
+// lp_i = sum_{m<=i} dlp_m, rho_i = C exp(lp_i)/T_i, f*_0 = f^eq(rho, g_vec/2, T - g^2/8).
+// Reverse: g_lp_i = g_rho_i rho_i; rc_i = sum_{m>=i} g_lp_m = total - prefix_{i-1};
+// g_T_i = g_Teq_i - g_rho_i rho_i / T_i + dfac_i (rc_i [i>=1] + rc_{i+1} [i<=n-2]),
+// dfac_i = g r / (2 T_i^2);  dJ/dh_f = sum_i g_T_i dT_i/dh_f.
+__device__ __forceinline__ double vjp_layer_t(const InitVjpArgs &a, double zc, double h0, double h1) {
+    const double s0 = 0.5 * (1.0 + tanh((zc - h0) / a.width));
+    const double s1 = 0.5 * (1.0 + tanh((zc - h1) / a.width));
+    return a.t_d + (a.t_m - a.t_d) * s0 + (a.t_u - a.t_m) * s1;
+}
+
+__device__ __forceinline__ double block_scan_incl(double v, double *red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < BLOCK; off <<= 1) {
+        const double add = tid >= off ? red[tid - off] : 0.0;
+        __syncthreads();
+        red[tid] += add;
+        __syncthreads();
+    }
+    const double out = red[tid];
+    __syncthreads();
+    return out;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int off = BLOCK / 2; off > 0; off >>= 1) {
+        if (tid < off) red[tid] += red[tid + off];
+        __syncthreads();
+    }
+    const double out = red[0];
+    __syncthreads();
+    return out;
+}
+
+__global__ __launch_bounds__(BLOCK) void init_vjp_columns(InitVjpArgs a) {
+    __shared__ double red[BLOCK];
+    __shared__ double heights[2];
+    const int x = blockIdx.x, tid = threadIdx.x;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    if (tid < 2) {
+        double h = (tid == 0 ? 1.0 : 2.0) * (double)a.lz / 3.0;
+        for (int j = 0; j < a.nmodes; ++j)
+            h += a.amp[tid * a.nmodes + j] *
+                 cos(2.0 * M_PI * (double)a.k[tid][j] * ((double)x + 0.5) / (double)a.lx + a.phase[tid][j]);
+        heights[tid] = h;
+    }
+    __syncthreads();
+    const double h0 = heights[0], h1 = heights[1];
+    const int n = a.lz + 3;
+
+    double total_glp = 0.0;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        double carry_lp = 0.0, carry_glp = 0.0, gh0 = 0.0, gh1 = 0.0;
+        for (int c0 = 0; c0 < n; c0 += BLOCK) {
+            const int i = c0 + tid;
+            const bool in = i < n;
+            const double zc = (double)(i - 3) + 0.5;
+            double T = 1.0, d = 0.0;
+            if (in) {
+                T = vjp_layer_t(a, zc, h0, h1);
+                if (i > 0) d = -a.g * R * 0.5 * (1.0 / vjp_layer_t(a, zc - 1.0, h0, h1) + 1.0 / T);
+            }
+            const double lp = carry_lp + block_scan_incl(d, red);
+            // the chunk's last prefix carries into the next chunk
+            if (tid == BLOCK - 1) red[0] = lp;
+            __syncthreads();
+            carry_lp = red[0];
+            __syncthreads();
+
+            double g_lp = 0.0, g_tdir = 0.0;
+            if (in && i >= 3) {
+                const size_t site = (size_t)x * a.lz + (size_t)(i - 3);
+                const double rho = a.norm * exp(lp) / T;
+                double lam[Q];
+#pragma unroll
+                for (int l = 0; l < Q; ++l) lam[l] = a.lam0[(size_t)l * N + site];
+                const double th = T - a.g * a.g / (4.0 * D) - 1.0;
+                const EqVjp s = eq_vjp_sums(lam, 0.0, -0.5 * a.g, th);
+                const double g_rho = s.sp, g_teq = rho * s.sth;
+                g_lp = g_rho * rho;
+                g_tdir = g_teq - g_rho * rho / T;
+            }
+            if (sweep == 0) {
+                total_glp += block_sum(g_lp, red);
+                continue;
+            }
+            // suffix sums rc_i = total - (prefix through i-1)
+            const double pre_incl = carry_glp + block_scan_incl(g_lp, red);
+            const double rc_i = total_glp - (pre_incl - g_lp);
+            const double rc_next = total_glp - pre_incl;
+            if (tid == BLOCK - 1) red[0] = pre_incl;
+            __syncthreads();
+            carry_glp = red[0];
+            __syncthreads();
+            double g_t = 0.0;
+            if (in) {
+                const double dfac = 0.5 * a.g * R / (T * T);
+                g_t = g_tdir + dfac * ((i >= 1 ? rc_i : 0.0) + (i <= n - 2 ? rc_next : 0.0));
+            }
+            const double y0 = (zc - h0) / a.width, y1 = (zc - h1) / a.width;
+            const double ch0 = cosh(y0), ch1 = cosh(y1);
+            const double dt_dh0 = -(a.t_m - a.t_d) * 0.5 / (ch0 * ch0) / a.width;
+            const double dt_dh1 = -(a.t_u - a.t_m) * 0.5 / (ch1 * ch1) / a.width;
+            gh0 += in ? g_t * dt_dh0 : 0.0;
+            gh1 += in ? g_t * dt_dh1 : 0.0;
+        }
+        if (sweep == 1) {
+            const double s0 = block_sum(gh0, red);
+            const double s1 = block_sum(gh1, red);
+            if (tid == 0) {
+                a.dh[x] = s0;
+                a.dh[a.lx + x] = s1;
+            }
+        }
+    }
+}
+
+// d amp[f][j] = sum_x dh[f][x] cos(2 pi k (x + 1/2)/Lx + phase); one block per (f, j)
+__global__ __launch_bounds__(BLOCK) void init_vjp_modes(InitVjpArgs a) {
+    __shared__ double red[BLOCK];
+    const int f = blockIdx.x / a.nmodes, j = blockIdx.x % a.nmodes;
+    double s = 0.0;
+    for (int x = threadIdx.x; x < a.lx; x += BLOCK)
+        s += a.dh[(size_t)f * a.lx + x] *
+             cos(2.0 * M_PI * (double)a.k[f][j] * ((double)x + 0.5) / (double)a.lx + a.phase[f][j]);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) a.d_amp[f * a.nmodes + j] = s;
+}
+
+hipError_t launch_init_vjp(const InitVjpArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(init_vjp_columns, dim3(a.lx), dim3(BLOCK), 0, s, a);
+    if (a.nmodes > 0) hipLaunchKernelGGL(init_vjp_modes, dim3(2 * a.nmodes), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

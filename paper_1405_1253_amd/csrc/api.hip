@@ -54,6 +54,49 @@ size_t state_bytes(const lbm_params *p) {
 size_t ghost_bytes(const lbm_params *p) { return (size_t)2 * 3 * LBM_Q * elt_size(p->precision); }
 size_t field_bytes(const lbm_params *p) { return (size_t)4 * p->lx * p->lz * sizeof(double); }
 
+// Unperturbed column, rows -3 .. Lz+2, on the host: the density
+// normalisation C and the wall rows.  Same construction as the device
+// columns: trapezoid rule for d ln p/dz = -g/T, one row = r length units.
+void host_profile(const lbm_params *p, const lbm_rt3_desc *d, double *norm, double ghost_rho[6],
+                  double ghost_t[6]) {
+    const int lz = p->lz, n = lz + 6;
+    std::vector<double> T(n), lnp(n);
+    for (int i = 0; i < n; ++i) {
+        const double zc = (double)(i - 3) + 0.5;
+        const double s0 = 0.5 * (1.0 + tanh((zc - lz / 3.0) / d->width));
+        const double s1 = 0.5 * (1.0 + tanh((zc - 2.0 * lz / 3.0) / d->width));
+        T[i] = d->t_d + (d->t_m - d->t_d) * s0 + (d->t_u - d->t_m) * s1;
+    }
+    lnp[0] = 0.0;
+    for (int i = 1; i < n; ++i) lnp[i] = lnp[i - 1] - p->g * lbm::R * 0.5 * (1.0 / T[i - 1] + 1.0 / T[i]);
+    double mean = 0.0;
+    for (int i = 3; i < 3 + lz; ++i) mean += exp(lnp[i]) / T[i];
+    mean /= (double)lz;
+    *norm = 1.0 / mean;
+    const int rows[6] = {2, 1, 0, 3 + lz, 4 + lz, 5 + lz};   // -1,-2,-3, Lz,Lz+1,Lz+2
+    for (int i = 0; i < 6; ++i) {
+        ghost_t[i] = T[rows[i]];
+        ghost_rho[i] = *norm * exp(lnp[rows[i]]) / T[rows[i]];
+    }
+}
+
+// Checks shared by the entry points that take an lbm_rt3_desc.
+int check_desc(const lbm_rt3_desc *d, const double *amp) {
+    if (!d) return LBM_EINVAL;
+    if (d->nmodes < 0 || d->nmodes > LBM_MAX_MODES || d->reserved != 0) return LBM_EINVAL;
+    if (d->nmodes > 0 && (!d->k || !d->phase || !amp)) return LBM_EINVAL;
+    if (!(d->width > 0.0) || !isfinite(d->width)) return LBM_EINVAL;
+    if (!(d->t_d > 0.0) || !(d->t_m > 0.0) || !(d->t_u > 0.0) || !isfinite(d->t_d) ||
+        !isfinite(d->t_m) || !isfinite(d->t_u))
+        return LBM_EINVAL;
+    for (int i = 0; i < 2 * d->nmodes; ++i)
+        if (!isfinite(d->phase[i])) return LBM_EINVAL;
+    return LBM_OK;
+}
+
+size_t lam_bytes(const lbm_params *p) { return (size_t)LBM_Q * p->lx * p->lz * sizeof(double); }
+size_t vjp_scratch_bytes(int lx) { return ((size_t)2 * lx * sizeof(double) + 255) & ~size_t(255); }
+
 }  // namespace
 
 extern "C" {
@@ -88,7 +131,10 @@ int lbm_lattice(double *r, double *w, int32_t *e) {
 size_t lbm_scratch_bytes(const lbm_params *p) {
     bool empty = false;
     if (check_params(p, &empty) != LBM_OK || empty) return 0;
-    return lbm::moments_scratch_bytes(p->lx, p->lz);
+    size_t b = lbm::moments_scratch_bytes(p->lx, p->lz);
+    if (lbm::objective_scratch_bytes(p->lx, p->lz) > b) b = lbm::objective_scratch_bytes(p->lx, p->lz);
+    if (vjp_scratch_bytes(p->lx) > b) b = vjp_scratch_bytes(p->lx);
+    return b;
 }
 
 int lbm_step(const lbm_params *p, const void *ghost, const void *f_in, void *f_out,
@@ -159,15 +205,8 @@ int lbm_init_rt3(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, 
     bool empty = false;
     int st = check_params(p, &empty);
     if (st != LBM_OK) return st;
-    if (!d || !f_out || !ghost_out) return LBM_EINVAL;
-    if (d->nmodes < 0 || d->nmodes > LBM_MAX_MODES || d->reserved != 0) return LBM_EINVAL;
-    if (d->nmodes > 0 && (!d->k || !d->phase || !amp)) return LBM_EINVAL;
-    if (!(d->width > 0.0) || !isfinite(d->width)) return LBM_EINVAL;
-    if (!(d->t_d > 0.0) || !(d->t_m > 0.0) || !(d->t_u > 0.0) || !isfinite(d->t_d) ||
-        !isfinite(d->t_m) || !isfinite(d->t_u))
-        return LBM_EINVAL;
-    for (int i = 0; i < 2 * d->nmodes; ++i)
-        if (!isfinite(d->phase[i])) return LBM_EINVAL;
+    if (!f_out || !ghost_out) return LBM_EINVAL;
+    if ((st = check_desc(d, amp)) != LBM_OK) return st;
     if (!aligned(f_out, 16) || !aligned(ghost_out, 8) || !aligned(amp, 8)) return LBM_EALIGN;
     if (overlap(f_out, state_bytes(p), ghost_out, ghost_bytes(p))) return LBM_EALIAS;
     if (empty) return LBM_OK;
@@ -191,29 +230,107 @@ int lbm_init_rt3(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, 
             a.phase[f][j] = d->phase[f * d->nmodes + j];
         }
 
-    // Unperturbed column, rows -3 .. Lz+2, on the host: the density
-    // normalisation and the wall rows.  Same construction as the columns:
-    // trapezoid rule for d ln p/dz = -g/T, one row = r length units.
-    const int lz = p->lz, n = lz + 6;
-    std::vector<double> T(n), lnp(n);
-    for (int i = 0; i < n; ++i) {
-        const double zc = (double)(i - 3) + 0.5;
-        const double s0 = 0.5 * (1.0 + tanh((zc - lz / 3.0) / d->width));
-        const double s1 = 0.5 * (1.0 + tanh((zc - 2.0 * lz / 3.0) / d->width));
-        T[i] = d->t_d + (d->t_m - d->t_d) * s0 + (d->t_u - d->t_m) * s1;
-    }
-    lnp[0] = 0.0;
-    for (int i = 1; i < n; ++i) lnp[i] = lnp[i - 1] - p->g * lbm::R * 0.5 * (1.0 / T[i - 1] + 1.0 / T[i]);
-    double mean = 0.0;
-    for (int i = 3; i < 3 + lz; ++i) mean += exp(lnp[i]) / T[i];
-    mean /= (double)lz;
-    a.norm = 1.0 / mean;
-    const int rows[6] = {2, 1, 0, 3 + lz, 4 + lz, 5 + lz};   // -1,-2,-3, Lz,Lz+1,Lz+2
-    for (int i = 0; i < 6; ++i) {
-        a.ghost_t[i] = T[rows[i]];
-        a.ghost_rho[i] = a.norm * exp(lnp[rows[i]]) / T[rows[i]];
-    }
+    host_profile(p, d, &a.norm, a.ghost_rho, a.ghost_t);
     return hip_status(lbm::launch_init(a, p->precision, (hipStream_t)stream));
+}
+
+int lbm_objective(const lbm_params *p, const lbm_rt3_desc *d, const void *f, double wk, double wl,
+                  double *j_out, double *lam_seed, void *scratch, size_t scratch_bytes,
+                  lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!d || !f || !j_out) return LBM_EINVAL;
+    if (!(d->t_d > d->t_m) || !(d->t_m > d->t_u) || !isfinite(d->t_d) || !isfinite(d->t_u))
+        return LBM_EINVAL;
+    if (!isfinite(wk) || !isfinite(wl)) return LBM_EINVAL;
+    if (!aligned(f, 16) || !aligned(j_out, 8) || !aligned(lam_seed, 16) || !aligned(scratch, 256))
+        return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const size_t need = lbm::objective_scratch_bytes(p->lx, p->lz);
+    if (!scratch || scratch_bytes < need) return LBM_ESCRATCH;
+    const size_t sb = state_bytes(p), lb = lam_bytes(p);
+    if (overlap(j_out, 24, f, sb) || overlap(lam_seed, lb, f, sb) || overlap(scratch, need, f, sb) ||
+        overlap(j_out, 24, lam_seed, lb) || overlap(j_out, 24, scratch, need) ||
+        overlap(lam_seed, lb, scratch, need))
+        return LBM_EALIAS;
+    lbm::ObjectiveArgs a;
+    a.f = f;
+    a.scratch = scratch;
+    a.j_out = j_out;
+    a.lam_seed = lam_seed;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.g = p->g;
+    a.t_d = d->t_d;
+    a.t_m = d->t_m;
+    a.t_u = d->t_u;
+    a.wk = wk;
+    a.wl = wl;
+    return hip_status(lbm::launch_objective(a, p->precision, (hipStream_t)stream));
+}
+
+int lbm_adjoint_step(const lbm_params *p, const double *moments, const double *lam_in, double *lam_out,
+                     lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!lam_in || !lam_out || (!moments && !(p->flags & LBM_NO_COLLIDE))) return LBM_EINVAL;
+    if (!aligned(lam_in, 16) || !aligned(lam_out, 16) || !aligned(moments, 16)) return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const size_t lb = lam_bytes(p), mb = field_bytes(p);
+    if (overlap(lam_in, lb, lam_out, lb) || overlap(moments, mb, lam_out, lb)) return LBM_EALIAS;
+    lbm::AdjointArgs a;
+    a.mom = moments;
+    a.lam_in = lam_in;
+    a.lam_out = lam_out;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.tau = p->tau;
+    a.omega = 1.0 / p->tau;
+    a.g = p->g;
+    a.flags = p->flags;
+    return hip_status(lbm::launch_adjoint_step(a, (hipStream_t)stream));
+}
+
+int lbm_init_rt3_vjp(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, const double *lam0,
+                     double *d_amp, void *scratch, size_t scratch_bytes, lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!lam0 || (!d_amp && d && d->nmodes > 0)) return LBM_EINVAL;
+    if ((st = check_desc(d, amp)) != LBM_OK) return st;
+    if (!aligned(lam0, 16) || !aligned(d_amp, 8) || !aligned(amp, 8) || !aligned(scratch, 256))
+        return LBM_EALIGN;
+    if (empty || d->nmodes == 0) return LBM_OK;
+    const size_t need = vjp_scratch_bytes(p->lx);
+    if (!scratch || scratch_bytes < need) return LBM_ESCRATCH;
+    const size_t ab = (size_t)2 * d->nmodes * sizeof(double), lb = lam_bytes(p);
+    if (overlap(d_amp, ab, lam0, lb) || overlap(d_amp, ab, amp, ab) || overlap(d_amp, ab, scratch, need) ||
+        overlap(scratch, need, lam0, lb) || overlap(scratch, need, amp, ab))
+        return LBM_EALIAS;
+    lbm::InitVjpArgs a;
+    memset(&a, 0, sizeof(a));
+    a.lam0 = lam0;
+    a.amp = amp;
+    a.d_amp = d_amp;
+    a.dh = static_cast<double *>(scratch);
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.nmodes = d->nmodes;
+    a.g = p->g;
+    a.t_d = d->t_d;
+    a.t_m = d->t_m;
+    a.t_u = d->t_u;
+    a.width = d->width;
+    for (int f = 0; f < 2; ++f)
+        for (int j = 0; j < d->nmodes; ++j) {
+            a.k[f][j] = d->k[f * d->nmodes + j];
+            a.phase[f][j] = d->phase[f * d->nmodes + j];
+        }
+    double gr[6], gt[6];
+    host_profile(p, d, &a.norm, gr, gt);
+    return hip_status(lbm::launch_init_vjp(a, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -22,7 +22,13 @@
 
 namespace lbm {
 
-constexpr int BLOCK = 256;   // threads per block, one site each along z
+#ifndef LBM_BLOCK
+#define LBM_BLOCK 256
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 1
+#endif
+constexpr int BLOCK = LBM_BLOCK;   // threads per block, one site each along z
 constexpr double D = 2.0;    // space dimension
 
 // Shell coefficients of the factored equilibrium.  A0m1 = A0 - 1 so that the
@@ -65,6 +71,22 @@ __device__ __forceinline__ void equilibrium_f64(double rho, double vx, double vz
     }
 }
 
+// Access at a wave-uniform base plus a 32-bit per-lane byte offset: lets the
+// compiler use the scalar-base form of global loads/stores (one shared
+// offset register instead of a 64-bit address per access).
+template <typename T>
+__device__ __forceinline__ T ldg_off(const T *base, uint32_t byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void stg_off(T *base, uint32_t byte_off, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+template <typename T>
+__device__ __forceinline__ void stg_off_nt(T *base, uint32_t byte_off, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
+}
+
 // Wrap an index into [0, n) for any integer (periodic directions).
 __device__ __forceinline__ int wrap(int i, int n) {
     int m = i % n;
@@ -75,6 +97,7 @@ __device__ __forceinline__ int wrap(int i, int n) {
 // (blocks are dealt round-robin over 8 XCDs) gets a contiguous range of
 // tiles: neighbouring tiles then share that XCD's L2.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
+    if (!LBM_XCD_REMAP) return b;
     const uint32_t nx = 8, q = nblocks / nx, rem = nblocks % nx;
     const uint32_t j = b % nx, i = b / nx;
     return (j < rem ? j * (q + 1) : rem * (q + 1) + (j - rem) * q) + i;

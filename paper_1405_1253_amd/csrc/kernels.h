@@ -48,4 +48,37 @@ struct InitArgs {
 };
 hipError_t launch_init(const InitArgs &a, int precision, hipStream_t s);
 
+struct AdjointArgs {
+    const double *mom;     // [4][lx][lz] pre-collision moments of the step
+    const double *lam_in;  // [37][lx][lz] dJ/df*_t
+    double *lam_out;       // [37][lx][lz] dJ/df*_{t-1}
+    int lx, lz;
+    double tau, omega, g;
+    uint32_t flags;
+};
+hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s);
+
+struct ObjectiveArgs {
+    const void *f;
+    void *scratch;
+    double *j_out;         // [3]: J, KE, L_u + L_d
+    double *lam_seed;      // nullable [37][lx][lz]
+    int lx, lz;
+    double g, t_d, t_m, t_u, wk, wl;
+};
+size_t objective_scratch_bytes(int lx, int lz);
+hipError_t launch_objective(const ObjectiveArgs &a, int precision, hipStream_t s);
+
+struct InitVjpArgs {
+    const double *lam0;    // [37][lx][lz]
+    const double *amp;     // [2][nmodes]
+    double *d_amp;         // [2][nmodes]
+    double *dh;            // scratch [2][lx]
+    int lx, lz, nmodes;
+    double g, t_d, t_m, t_u, width, norm;
+    int k[2][MAX_MODES];
+    double phase[2][MAX_MODES];
+};
+hipError_t launch_init_vjp(const InitVjpArgs &a, hipStream_t s);
+
 }  // namespace lbm

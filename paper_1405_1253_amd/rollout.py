@@ -1,0 +1,148 @@
+"""Differentiable N-step rollout: J(amp) and dJ/d amp through the HIP adjoint.
+
+J = wk * KE(f*_N) + wl * (L_u + L_d)(f*_N) for f*_N = step^N(init_rt3(amp)),
+with the mixing lengths of Sec. IV (eq. 3L).  The backward pass runs the
+library's adjoint kernels (lbm_objective seed, lbm_adjoint_step,
+lbm_init_rt3_vjp); this module only schedules them and manages memory.
+
+Memory schedule (two levels):
+* level 1 -- the state f*_t is checkpointed every ``ckpt_every`` steps during
+  the forward pass (the initial state is checkpoint 0);
+* level 2 -- the adjoint of step t needs the 4 pre-collision moments of that
+  step.  The forward pass keeps them for the last ``keep`` steps (as many as
+  ``moment_budget_bytes`` allows); for earlier steps each checkpoint segment
+  is recomputed from its checkpoint, storing its moments, just before the
+  backward sweep crosses it.
+With every step's moments kept the backward pass needs no recomputation.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import abi
+from .workload import Workload
+
+
+@dataclass
+class RolloutConfig:
+    lx: int
+    lz: int
+    tau: float
+    g: float
+    t_d: float
+    t_m: float
+    t_u: float
+    width: float
+    k: np.ndarray
+    phase: np.ndarray
+    nsteps: int
+    ckpt_every: int = 100
+    precision: str = "f64"
+    wk: float = 1.0
+    wl: float = 1.0
+    moment_budget_bytes: int = 64 << 30
+
+    @classmethod
+    def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
+        kw.setdefault("ckpt_every", wl.ckpt_every or 100)
+        kw.setdefault("precision", wl.precision)
+        return cls(wl.lx, wl.lz, wl.tau, wl.g, wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k,
+                   modes.phase, wl.steps if nsteps is None else nsteps, **kw)
+
+
+class Rollout:
+    """Forward/backward driver with checkpointing (one GPU)."""
+
+    def __init__(self, cfg: RolloutConfig, device="cuda"):
+        self.cfg = c = cfg
+        self.device = torch.device(device)
+        self.params = abi.make_params(c.lx, c.lz, c.tau, c.g,
+                                      abi.F64 if c.precision == "f64" else abi.F32_DEV)
+        self.desc = abi.RT3Desc(c.t_d, c.t_m, c.t_u, c.width, c.k, c.phase)
+        self.sdtype = torch.float64 if c.precision == "f64" else torch.float32
+        shape = (abi.Q, c.lx, c.lz)
+        self.buf = [torch.empty(shape, dtype=self.sdtype, device=self.device) for _ in range(2)]
+        self.ghost = torch.empty((2, 3, abi.Q), dtype=self.sdtype, device=self.device)
+        self.scratch = torch.empty(max(abi.lbm_scratch_bytes(self.params), 256), dtype=torch.uint8,
+                                   device=self.device)
+        mbytes = 4 * c.lx * c.lz * 8
+        self.keep = int(min(c.nsteps, c.moment_budget_bytes // mbytes))
+        self.first_kept = c.nsteps - self.keep + 1          # steps >= this keep their moments
+        self.kept = torch.empty((self.keep, 4, c.lx, c.lz), dtype=torch.float64, device=self.device)
+        seg = 0 if self.keep >= c.nsteps else c.ckpt_every
+        self.segbuf = torch.empty((seg, 4, c.lx, c.lz), dtype=torch.float64, device=self.device)
+        self.ckpt = {}
+        self.recomputed_steps = 0
+
+    # ---- forward ----------------------------------------------------------
+    def _step(self, src, dst, mom=None):
+        abi.lbm_step(self.params, self.ghost, src, dst, mom)
+
+    def _mom_slot(self, t):
+        return self.kept[t - self.first_kept] if t >= self.first_kept else None
+
+    def forward(self, amp):
+        c = self.cfg
+        self.amp = amp.detach().to(self.device, torch.float64).contiguous()
+        abi.lbm_init_rt3(self.params, self.desc, self.amp, self.buf[0], self.ghost)
+        cur = 0
+        self.ckpt = {0: self.buf[0].clone()}
+        for t in range(1, c.nsteps + 1):
+            self._step(self.buf[cur], self.buf[1 - cur], self._mom_slot(t))
+            cur = 1 - cur
+            if t % c.ckpt_every == 0 and t < c.nsteps and t < self.first_kept:
+                self.ckpt[t] = self.buf[cur].clone()
+        self.final = self.buf[cur]
+        self.j = torch.empty(3, dtype=torch.float64, device=self.device)
+        self.lam = [torch.empty((abi.Q, c.lx, c.lz), dtype=torch.float64, device=self.device)
+                    for _ in range(2)]
+        abi.lbm_objective(self.params, self.desc, self.final, c.wk, c.wl, self.j, self.lam[0],
+                          self.scratch)
+        return self.j
+
+    # ---- backward ---------------------------------------------------------
+    def backward(self):
+        """dJ/d amp [2, nmodes] (device float64)."""
+        c = self.cfg
+        li = 0
+        t = c.nsteps
+        while t >= 1:
+            if t >= self.first_kept:
+                abi.lbm_adjoint_step(self.params, self.kept[t - self.first_kept], self.lam[li],
+                                     self.lam[1 - li])
+                li = 1 - li
+                t -= 1
+                continue
+            # recompute the checkpoint segment (a, b] that contains t
+            a = ((t - 1) // c.ckpt_every) * c.ckpt_every
+            b = t
+            self.buf[0].copy_(self.ckpt[a])
+            cur = 0
+            for s in range(a + 1, b + 1):
+                self._step(self.buf[cur], self.buf[1 - cur], self.segbuf[s - a - 1])
+                cur = 1 - cur
+            self.recomputed_steps += b - a
+            for s in range(b, a, -1):
+                abi.lbm_adjoint_step(self.params, self.segbuf[s - a - 1], self.lam[li],
+                                     self.lam[1 - li])
+                li = 1 - li
+            t = a
+        d_amp = torch.empty_like(self.amp)
+        abi.lbm_init_rt3_vjp(self.params, self.desc, self.amp, self.lam[li], d_amp, self.scratch)
+        return d_amp
+
+
+class RTRollout(torch.autograd.Function):
+    """J = RTRollout.apply(amp, rollout): autograd entry point; the backward
+    pass returns grad_J * dJ/d amp from the HIP adjoint."""
+
+    @staticmethod
+    def forward(ctx, amp, rollout):
+        ctx.rollout = rollout
+        return rollout.forward(amp)[0].clone()
+
+    @staticmethod
+    def backward(ctx, grad):
+        d_amp = ctx.rollout.backward()
+        return grad * d_amp, None

@@ -42,8 +42,8 @@ class Lattice:
         if not torch.is_tensor(amp):
             amp = torch.as_tensor(np.asarray(amp, dtype=np.float64), device=self.device)
         amp = amp.to(device=self.device, dtype=torch.float64).contiguous()
-        abi.lbm_init_rt3(self.params, t_d, t_m, t_u, width, k, phase, amp,
-                         self.buf[0], self.ghost)
+        self.desc = abi.RT3Desc(t_d, t_m, t_u, width, k, phase)
+        abi.lbm_init_rt3(self.params, self.desc, amp, self.buf[0], self.ghost)
         self.cur = 0
         self.steps_done = 0
         self._amp = amp   # keep alive until the stream has consumed it

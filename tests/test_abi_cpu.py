@@ -89,7 +89,7 @@ def test_moments_and_init_reject_bad_arguments(abi):
     need = abi.lbm_scratch_bytes(p)
     assert need > 0
     # sums requested with a scratch buffer that is too small
-    st = lib.lbm_moments(ctypes.byref(p), 1 << 30, None, None, 1 << 20, 3 << 30, need - 8, None)
+    st = lib.lbm_moments(ctypes.byref(p), 1 << 30, None, None, 1 << 20, 3 << 30, 64, None)
     assert st == -5
     st = lib.lbm_moments(ctypes.byref(p), 1 << 30, None, None, 1 << 20, None, 0, None)
     assert st == -5
@@ -102,6 +102,17 @@ def test_moments_and_init_reject_bad_arguments(abi):
     desc.nmodes = 16
     desc.width = 0.0
     assert lib.lbm_init_rt3(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 3 << 30, None) == -1
+    desc.width = 4.0
+    # objective needs t_d > t_m > t_u and scratch; adjoint needs moments unless NO_COLLIDE
+    bad = abi.lbm_rt3_desc(0.95, 1.0, 1.05, 4.0, 0, 0, None, None)
+    assert lib.lbm_objective(ctypes.byref(p), ctypes.byref(bad), 1 << 30, 1.0, 1.0, 1 << 20, None,
+                             3 << 30, need, None) == -1
+    assert lib.lbm_objective(ctypes.byref(p), ctypes.byref(desc), 1 << 30, 1.0, 1.0, 1 << 20, None,
+                             3 << 30, 64, None) == -5
+    assert lib.lbm_adjoint_step(ctypes.byref(p), None, 1 << 30, 3 << 30, None) == -1
+    assert lib.lbm_adjoint_step(ctypes.byref(p), 1 << 20, 1 << 30, (1 << 30) + 4096, None) == -2
+    assert lib.lbm_init_rt3_vjp(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 1 << 19,
+                                3 << 30, 8, None) == -5
 
 
 def test_error_strings(abi):

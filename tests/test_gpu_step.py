@@ -40,7 +40,7 @@ def _gpu_init(abi, lat_p, m, t=(1.05, 1.0, 0.95), width=4.0, dtype=torch.float64
     f = torch.empty((37, lx, lz), dtype=dtype, device=DEV)
     ghost = torch.empty((2, 3, 37), dtype=dtype, device=DEV)
     amp = torch.as_tensor(m.amp, device=DEV)
-    abi.lbm_init_rt3(lat_p, t[0], t[1], t[2], width, m.k, m.phase, amp, f, ghost)
+    abi.lbm_init_rt3(lat_p, abi.RT3Desc(t[0], t[1], t[2], width, m.k, m.phase), amp, f, ghost)
     return f, ghost
 
 
