@@ -95,6 +95,63 @@ def cpu_baseline(wl, columns=16, steps=8):
                       f"lattice (numpy FP64 oracle, 1 thread, {dt:.1f} s)"}
 
 
+def adjoint_ratio(name, budget_bytes=None, warm=True):
+    """Wall time of the rollout's forward pass (with checkpoints and stored
+    moments) and of its backward pass (recomputation + adjoint sweep + init
+    VJP), against a plain forward of the same steps (one run each, after one
+    warm-up run of every phase if ``warm``)."""
+    import torch
+    from paper_1405_1253_amd.rollout import Rollout, RolloutConfig
+    from paper_1405_1253_amd.runtime import Lattice
+    from paper_1405_1253_amd.workload import WORKLOADS, draw_modes
+    wl = WORKLOADS[name]
+    m = draw_modes(wl.seed)
+    kw = {} if budget_bytes is None else {"moment_budget_bytes": budget_bytes}
+    amp = torch.as_tensor(m.amp, device="cuda")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    lat = Lattice.from_workload(wl, modes=m)
+    lat.step(wl.steps if warm else 2)                   # warm-up
+    t_plain, _ = timed(lambda: lat.step(wl.steps))
+    del lat
+    torch.cuda.empty_cache()
+    r = Rollout(RolloutConfig.from_workload(wl, m, **kw))
+    if warm:
+        r.forward(amp)
+        r.backward()
+    r.recomputed_steps = 0
+    t_fwd, _ = timed(lambda: r.forward(amp))
+    t_bwd, grad = timed(r.backward)
+    out = {"workload": name, "steps": wl.steps, "plain_forward_s": round(t_plain, 4),
+           "rollout_forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
+           "backward_over_plain_forward": round(t_bwd / t_plain, 3),
+           "gradient_over_plain_forward": round((t_fwd + t_bwd) / t_plain, 3),
+           "recomputed_steps": r.recomputed_steps, "moments_kept": r.keep,
+           "grad_finite": bool(torch.isfinite(grad).all().item())}
+    del r
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_calibration(nbytes=4 << 30, reps=3):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": nbytes, "copy_calibration_bytes_written": nbytes,
+                      "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,7 +160,13 @@ def main():
     ap.add_argument("--workload", default="rt3_4096x12288")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain copy of known size (for the HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU x-slab "
               "decomposition is not part of this build.", file=sys.stderr)
@@ -153,6 +216,9 @@ def main():
                                 "f32dev_ms_per_step": round(s32 / args.steps * 1e3, 4),
                                 "f32dev_hbm_gbs": round(a32, 1),
                                 "f32dev_frac": round(a32 / HBM_PEAK_GBS, 4)}
+    if not args.no_adjoint:
+        out["adjoint"] = [adjoint_ratio("rt3_512x1536_adj"),
+                          adjoint_ratio("rt3_2048x6144_adj", 60 << 30, warm=False)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

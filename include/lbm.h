@@ -81,8 +81,10 @@ enum lbm_status {
 enum lbm_precision { LBM_F64 = 0, LBM_F32_DEV = 1 };
 
 enum lbm_flags {
-    LBM_PERIODIC_Z = 1u, /* test mode: z wraps like x, no walls, ghost unused */
-    LBM_NO_COLLIDE = 2u  /* test mode: streaming and walls only               */
+    LBM_PERIODIC_Z = 1u, /* test mode: z wraps like x, no walls, ghost unused           */
+    LBM_NO_COLLIDE = 2u, /* test mode: streaming and walls only                          */
+    LBM_ADJ_F32 = 4u     /* adjoint buffers (lam_seed, lam_in/lam_out, lam0) are float,
+                            not double; the adjoint arithmetic stays double            */
 };
 
 typedef struct lbm_params {
@@ -194,13 +196,14 @@ int lbm_moments(const lbm_params *params, const void *f, double *fields, double 
  *   desc      (host) only t_d > t_m > t_u are used
  *   f         (device) state buffer
  *   j_out     (device) double [3]: J, KE, L_u + L_d
- *   lam_seed  (device, nullable) double [37][Lx][Lz]: dJ/df_l at every site
+ *   lam_seed  (device, nullable) [37][Lx][Lz] (double, or float with LBM_ADJ_F32):
+ *             dJ/df_l at every site
  *             (the tent map's slope is taken as 2, -2, 0 on the three pieces)
  *   scratch   (device) at least lbm_scratch_bytes(params) bytes
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.
  */
 int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void *f, double wk, double wl,
-                  double *j_out, double *lam_seed, void *scratch, size_t scratch_bytes,
+                  double *j_out, void *lam_seed, void *scratch, size_t scratch_bytes,
                   lbm_stream_t stream);
 
 /*
@@ -218,14 +221,14 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  *
  *   moments  (device) double [4][Lx][Lz]: rho, u_x, u_z, T written by the
  *            forward lbm_step's moments_out (may be NULL with LBM_NO_COLLIDE)
- *   lam_in   (device) double [37][Lx][Lz]
- *   lam_out  (device) double [37][Lx][Lz], must not overlap lam_in or moments
- * The adjoint is always double; params->precision only names the forward
- * state it belongs to.
+ *   lam_in   (device) [37][Lx][Lz], double (float with LBM_ADJ_F32)
+ *   lam_out  (device) same type and shape, must not overlap lam_in or moments
+ * The adjoint arithmetic is double; params->precision only names the
+ * forward state it belongs to.
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
  */
-int lbm_adjoint_step(const lbm_params *params, const double *moments, const double *lam_in,
-                     double *lam_out, lbm_stream_t stream);
+int lbm_adjoint_step(const lbm_params *params, const double *moments, const void *lam_in,
+                     void *lam_out, lbm_stream_t stream);
 
 /*
  * lbm_init_rt3_vjp -- gradient of lbm_init_rt3 with respect to the mode
@@ -234,13 +237,13 @@ int lbm_adjoint_step(const lbm_params *params, const double *moments, const doub
  * equilibrium (Sec. I, eq. seteq).  The wall table does not depend on amp.
  *
  *   desc, amp  as passed to lbm_init_rt3
- *   lam0       (device) double [37][Lx][Lz]: dJ/df*_0
+ *   lam0       (device) [37][Lx][Lz] (double, or float with LBM_ADJ_F32): dJ/df*_0
  *   d_amp      (device) double [2][nmodes], written
  *   scratch    (device) at least lbm_scratch_bytes(params) bytes
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.
  */
 int lbm_init_rt3_vjp(const lbm_params *params, const lbm_rt3_desc *desc, const double *amp,
-                     const double *lam0, double *d_amp, void *scratch, size_t scratch_bytes,
+                     const void *lam0, double *d_amp, void *scratch, size_t scratch_bytes,
                      lbm_stream_t stream);
 
 /*

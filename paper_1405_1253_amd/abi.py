@@ -18,7 +18,7 @@ ABI_VERSION = 1
 Q = 37
 MAX_MODES = 32
 F64, F32_DEV = 0, 1
-PERIODIC_Z, NO_COLLIDE = 1, 2
+PERIODIC_Z, NO_COLLIDE, ADJ_F32 = 1, 2, 4
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EALIAS", -3: "LBM_EALIGN",
           -4: "LBM_EHIP", -5: "LBM_ESCRATCH", -6: "LBM_EVERSION"}

@@ -87,18 +87,21 @@ __device__ __forceinline__ EqVjp eq_vjp_sums(const double lam[Q], double vx, dou
 // ---------------------------------------------------------------------------
 // adjoint step
 // ---------------------------------------------------------------------------
-template <bool EDGE>
+template <bool EDGE, typename L>
 __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0) {
+    const L *__restrict__ lam_in = static_cast<const L *>(a.lam_in);
+    L *__restrict__ lam_out = static_cast<L *>(a.lam_out);
     const size_t N = (size_t)a.lx * (size_t)a.lz;
     const int z = z0 + (int)threadIdx.x;
     if (EDGE && z >= a.lz) return;
     const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
     // uniform column base + 32-bit per-lane byte offset for every access
     const uint32_t zoff = (uint32_t)z * 8u;
+    const uint32_t loff = (uint32_t)z * (uint32_t)sizeof(L);
     double lam[Q];
 #pragma unroll
     for (int l = 0; l < Q; ++l)
-        lam[l] = ldg_off(a.lam_in + (size_t)l * N + (size_t)x * (size_t)a.lz, zoff);
+        lam[l] = (double)ldg_off(lam_in + (size_t)l * N + (size_t)x * (size_t)a.lz, loff);
 
     // G_l = keep lam_l + alpha + beta . xi_l + gamma |xi_l|^2 (NO_COLLIDE: G = lam)
     double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
@@ -124,12 +127,12 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
 
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const double G = keep * lam[l] + alpha + (EX[l] * bx + EZ[l] * bz) + gamma * XI2_SHELL[SHELL[l]];
+        const L G = (L)(keep * lam[l] + alpha + (EX[l] * bx + EZ[l] * bz) + gamma * XI2_SHELL[SHELL[l]]);
         const int xd = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
         const int zd = z - EZ[l];
-        double *dst = a.lam_out + (size_t)l * N + (size_t)xd * (size_t)a.lz;
+        L *dst = lam_out + (size_t)l * N + (size_t)xd * (size_t)a.lz;
         if (!EDGE) {
-            stg_off(dst - EZ[l], zoff, G);
+            stg_off(dst - EZ[l], loff, G);
         } else if (a.flags & F_PERIODIC_Z) {
             dst[wrap(zd, a.lz)] = G;
         } else {
@@ -137,24 +140,28 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
             // lam_out_l(z) = G_l(z + e_lz) has no writer when row z + e_lz lies
             // beyond a wall: that pull read the constant wall table
             const int zsrc = z + EZ[l];
-            if (zsrc < 0 || zsrc >= a.lz) a.lam_out[(size_t)l * N + site] = 0.0;
+            if (zsrc < 0 || zsrc >= a.lz) lam_out[(size_t)l * N + site] = L(0);
         }
     }
 }
 
+template <typename L>
 __global__ __launch_bounds__(BLOCK) void adjoint_step_kernel(AdjointArgs a, int nzb) {
     const int x = (int)(blockIdx.x / (uint32_t)nzb);
     const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BLOCK;
     if ((z0 < 3) || (z0 + BLOCK + 3 > a.lz))
-        adjoint_tile<true>(a, x, z0);
+        adjoint_tile<true, L>(a, x, z0);
     else
-        adjoint_tile<false>(a, x, z0);
+        adjoint_tile<false, L>(a, x, z0);
 }
 
 hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
     const int nzb = (a.lz + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(adjoint_step_kernel, dim3((uint32_t)nzb * (uint32_t)a.lx), dim3(BLOCK), 0, s, a,
-                       nzb);
+    const dim3 grid((uint32_t)nzb * (uint32_t)a.lx);
+    if (a.flags & F_ADJ_F32)
+        hipLaunchKernelGGL(adjoint_step_kernel<float>, grid, dim3(BLOCK), 0, s, a, nzb);
+    else
+        hipLaunchKernelGGL(adjoint_step_kernel<double>, grid, dim3(BLOCK), 0, s, a, nzb);
     return hipGetLastError();
 }
 
@@ -282,8 +289,9 @@ __global__ __launch_bounds__(BLOCK) void objective_pass2(ObjectiveArgs a, ObjLay
 
 // Seed lam_N = dJ/df*: dJ/drho = wk |u^H|^2/2, dJ/du* = wk rho u^H,
 // dJ/dT* = dJ/dT(z) / Lx, chained through the moment Jacobian.
-template <int PREC>
+template <int PREC, typename LT>
 __global__ __launch_bounds__(BLOCK) void objective_seed(ObjectiveArgs a, ObjLayout L) {
+    LT *lam_seed = static_cast<LT *>(a.lam_seed);
     const double *dtbar = reinterpret_cast<const double *>(static_cast<char *>(a.scratch) + L.dtbar);
     const int x = blockIdx.x / L.nzb, z = (blockIdx.x % L.nzb) * BLOCK + threadIdx.x;
     if (z >= a.lz) return;
@@ -298,8 +306,8 @@ __global__ __launch_bounds__(BLOCK) void objective_seed(ObjectiveArgs a, ObjLayo
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
         const double cx = R * EX[l] - ux, cz = R * EZ[l] - uz;
-        a.lam_seed[(size_t)l * N + site] =
-            g_rho + (gux * cx + guz * cz) * inv + g_t * (cx * cx + cz * cz - D * T) * idr;
+        lam_seed[(size_t)l * N + site] =
+            (LT)(g_rho + (gux * cx + guz * cz) * inv + g_t * (cx * cx + cz * cz - D * T) * idr);
     }
 }
 
@@ -312,10 +320,14 @@ hipError_t launch_objective(const ObjectiveArgs &a, int precision, hipStream_t s
     hipLaunchKernelGGL(objective_pass2, dim3(1), dim3(BLOCK), 0, s, a, L);
     if (a.lam_seed) {
         const dim3 g((uint32_t)L.nzb * (uint32_t)a.lx);
-        if (precision == P_F64)
-            hipLaunchKernelGGL(objective_seed<P_F64>, g, dim3(BLOCK), 0, s, a, L);
+        if (precision == P_F64 && !a.lam_f32)
+            hipLaunchKernelGGL((objective_seed<P_F64, double>), g, dim3(BLOCK), 0, s, a, L);
+        else if (precision == P_F64)
+            hipLaunchKernelGGL((objective_seed<P_F64, float>), g, dim3(BLOCK), 0, s, a, L);
+        else if (!a.lam_f32)
+            hipLaunchKernelGGL((objective_seed<P_F32_DEV, double>), g, dim3(BLOCK), 0, s, a, L);
         else
-            hipLaunchKernelGGL(objective_seed<P_F32_DEV>, g, dim3(BLOCK), 0, s, a, L);
+            hipLaunchKernelGGL((objective_seed<P_F32_DEV, float>), g, dim3(BLOCK), 0, s, a, L);
     }
     return hipGetLastError();
 }
@@ -363,7 +375,9 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return out;
 }
 
+template <typename LT>
 __global__ __launch_bounds__(BLOCK) void init_vjp_columns(InitVjpArgs a) {
+    const LT *lam0 = static_cast<const LT *>(a.lam0);
     __shared__ double red[BLOCK];
     __shared__ double heights[2];
     const int x = blockIdx.x, tid = threadIdx.x;
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(BLOCK) void init_vjp_columns(InitVjpArgs a) {
                 const double rho = a.norm * exp(lp) / T;
                 double lam[Q];
 #pragma unroll
-                for (int l = 0; l < Q; ++l) lam[l] = a.lam0[(size_t)l * N + site];
+                for (int l = 0; l < Q; ++l) lam[l] = (double)lam0[(size_t)l * N + site];
                 const double th = T - a.g * a.g / (4.0 * D) - 1.0;
                 const EqVjp s = eq_vjp_sums(lam, 0.0, -0.5 * a.g, th);
                 const double g_rho = s.sp, g_teq = rho * s.sth;
@@ -459,7 +473,10 @@ __global__ __launch_bounds__(BLOCK) void init_vjp_modes(InitVjpArgs a) {
 }
 
 hipError_t launch_init_vjp(const InitVjpArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(init_vjp_columns, dim3(a.lx), dim3(BLOCK), 0, s, a);
+    if (a.lam_f32)
+        hipLaunchKernelGGL(init_vjp_columns<float>, dim3(a.lx), dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL(init_vjp_columns<double>, dim3(a.lx), dim3(BLOCK), 0, s, a);
     if (a.nmodes > 0) hipLaunchKernelGGL(init_vjp_modes, dim3(2 * a.nmodes), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }

@@ -32,7 +32,7 @@ int check_params(const lbm_params *p, bool *empty) {
     if (p->lx < 0 || p->lz < 0) return LBM_EINVAL;
     if ((long long)p->lx * (long long)p->lz > MAX_SITES) return LBM_EINVAL;
     if (p->precision != LBM_F64 && p->precision != LBM_F32_DEV) return LBM_EINVAL;
-    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE)) return LBM_EINVAL;
+    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32)) return LBM_EINVAL;
     if (p->reserved != 0) return LBM_EINVAL;
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return LBM_EINVAL;
     if (!(p->g >= 0.0) || !isfinite(p->g)) return LBM_EINVAL;
@@ -94,7 +94,9 @@ int check_desc(const lbm_rt3_desc *d, const double *amp) {
     return LBM_OK;
 }
 
-size_t lam_bytes(const lbm_params *p) { return (size_t)LBM_Q * p->lx * p->lz * sizeof(double); }
+size_t lam_bytes(const lbm_params *p) {
+    return (size_t)LBM_Q * p->lx * p->lz * ((p->flags & LBM_ADJ_F32) ? sizeof(float) : sizeof(double));
+}
 size_t vjp_scratch_bytes(int lx) { return ((size_t)2 * lx * sizeof(double) + 255) & ~size_t(255); }
 
 }  // namespace
@@ -235,7 +237,7 @@ int lbm_init_rt3(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, 
 }
 
 int lbm_objective(const lbm_params *p, const lbm_rt3_desc *d, const void *f, double wk, double wl,
-                  double *j_out, double *lam_seed, void *scratch, size_t scratch_bytes,
+                  double *j_out, void *lam_seed, void *scratch, size_t scratch_bytes,
                   lbm_stream_t stream) {
     bool empty = false;
     int st = check_params(p, &empty);
@@ -259,6 +261,7 @@ int lbm_objective(const lbm_params *p, const lbm_rt3_desc *d, const void *f, dou
     a.scratch = scratch;
     a.j_out = j_out;
     a.lam_seed = lam_seed;
+    a.lam_f32 = (p->flags & LBM_ADJ_F32) != 0;
     a.lx = p->lx;
     a.lz = p->lz;
     a.g = p->g;
@@ -270,7 +273,7 @@ int lbm_objective(const lbm_params *p, const lbm_rt3_desc *d, const void *f, dou
     return hip_status(lbm::launch_objective(a, p->precision, (hipStream_t)stream));
 }
 
-int lbm_adjoint_step(const lbm_params *p, const double *moments, const double *lam_in, double *lam_out,
+int lbm_adjoint_step(const lbm_params *p, const double *moments, const void *lam_in, void *lam_out,
                      lbm_stream_t stream) {
     bool empty = false;
     int st = check_params(p, &empty);
@@ -293,7 +296,7 @@ int lbm_adjoint_step(const lbm_params *p, const double *moments, const double *l
     return hip_status(lbm::launch_adjoint_step(a, (hipStream_t)stream));
 }
 
-int lbm_init_rt3_vjp(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, const double *lam0,
+int lbm_init_rt3_vjp(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, const void *lam0,
                      double *d_amp, void *scratch, size_t scratch_bytes, lbm_stream_t stream) {
     bool empty = false;
     int st = check_params(p, &empty);
@@ -312,6 +315,7 @@ int lbm_init_rt3_vjp(const lbm_params *p, const lbm_rt3_desc *d, const double *a
     lbm::InitVjpArgs a;
     memset(&a, 0, sizeof(a));
     a.lam0 = lam0;
+    a.lam_f32 = (p->flags & LBM_ADJ_F32) != 0;
     a.amp = amp;
     a.d_amp = d_amp;
     a.dh = static_cast<double *>(scratch);

@@ -8,7 +8,7 @@
 
 namespace lbm {
 
-enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u };
+enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u };
 enum : int { P_F64 = 0, P_F32_DEV = 1 };
 
 struct StepArgs {
@@ -50,8 +50,8 @@ hipError_t launch_init(const InitArgs &a, int precision, hipStream_t s);
 
 struct AdjointArgs {
     const double *mom;     // [4][lx][lz] pre-collision moments of the step
-    const double *lam_in;  // [37][lx][lz] dJ/df*_t
-    double *lam_out;       // [37][lx][lz] dJ/df*_{t-1}
+    const void *lam_in;    // [37][lx][lz] dJ/df*_t (double, or float with F_ADJ_F32)
+    void *lam_out;         // [37][lx][lz] dJ/df*_{t-1}
     int lx, lz;
     double tau, omega, g;
     uint32_t flags;
@@ -62,15 +62,17 @@ struct ObjectiveArgs {
     const void *f;
     void *scratch;
     double *j_out;         // [3]: J, KE, L_u + L_d
-    double *lam_seed;      // nullable [37][lx][lz]
+    void *lam_seed;        // nullable [37][lx][lz], double or float
     int lx, lz;
+    bool lam_f32;
     double g, t_d, t_m, t_u, wk, wl;
 };
 size_t objective_scratch_bytes(int lx, int lz);
 hipError_t launch_objective(const ObjectiveArgs &a, int precision, hipStream_t s);
 
 struct InitVjpArgs {
-    const double *lam0;    // [37][lx][lz]
+    const void *lam0;      // [37][lx][lz], double or float
+    bool lam_f32;
     const double *amp;     // [2][nmodes]
     double *d_amp;         // [2][nmodes]
     double *dh;            // scratch [2][lx]

@@ -42,6 +42,7 @@ class RolloutConfig:
     wk: float = 1.0
     wl: float = 1.0
     moment_budget_bytes: int = 64 << 30
+    adj_precision: str = "f64"     # "f32": adjoint buffers in float (LBM_ADJ_F32)
 
     @classmethod
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
@@ -58,7 +59,9 @@ class Rollout:
         self.cfg = c = cfg
         self.device = torch.device(device)
         self.params = abi.make_params(c.lx, c.lz, c.tau, c.g,
-                                      abi.F64 if c.precision == "f64" else abi.F32_DEV)
+                                      abi.F64 if c.precision == "f64" else abi.F32_DEV,
+                                      abi.ADJ_F32 if c.adj_precision == "f32" else 0)
+        self.ldtype = torch.float32 if c.adj_precision == "f32" else torch.float64
         self.desc = abi.RT3Desc(c.t_d, c.t_m, c.t_u, c.width, c.k, c.phase)
         self.sdtype = torch.float64 if c.precision == "f64" else torch.float32
         shape = (abi.Q, c.lx, c.lz)
@@ -95,7 +98,7 @@ class Rollout:
                 self.ckpt[t] = self.buf[cur].clone()
         self.final = self.buf[cur]
         self.j = torch.empty(3, dtype=torch.float64, device=self.device)
-        self.lam = [torch.empty((abi.Q, c.lx, c.lz), dtype=torch.float64, device=self.device)
+        self.lam = [torch.empty((abi.Q, c.lx, c.lz), dtype=self.ldtype, device=self.device)
                     for _ in range(2)]
         abi.lbm_objective(self.params, self.desc, self.final, c.wk, c.wl, self.j, self.lam[0],
                           self.scratch)
