@@ -31,56 +31,88 @@
 
 namespace lbm {
 
-// sum_l lam_l w_l {P_l, dP_l/dx xi_l, dP_l/du2, dP_l/dth} at (v, th)
+// sum_l lam_l w_l {P_l, dP_l/dx xi_l, dP_l/du2, dP_l/dth} at (v, th).
+//
+// P is a polynomial of degree 4 in xi (through x = xi . v and xi2 = |xi|^2),
+// so every sum is a fixed polynomial in (v, u2, th) contracted with the 15
+// raw moments m_pq = sum_l lam_l w_l xi_x^p xi_z^q, p + q <= 4.  With
+//   A0 = a0 + a1 xi2 + a2 xi2^2, A1 = b0 + b1 xi2, A2 = c0 + c1 xi2,
+//   a0 = 1 - u2/2 - th + u2^2/8 + th u2 + th^2, a1 = th/2 - th u2/4 - th^2,
+//   a2 = th^2/8, b0 = 1 - u2/2 - 2 th, b1 = th/2, c0 = 1/2 - u2/4 - 3 th/2,
+//   c1 = th/4,
+// and the shorthand M_f = sum_l lam_l w_l f(xi_l):
+//   sum P        = a0 M_1 + a1 M_xi2 + a2 M_xi2^2 + b0 M_x + b1 M_xi2x + c0 M_x^2
+//                  + c1 M_xi2x^2 + M_x^3/6 + M_x^4/24
+//   sum P' xi_i  = b0 M_i + b1 M_xi2 i + 2 c0 M_x i + 2 c1 M_xi2 x i + M_x^2 i/2 + M_x^3 i/6
+//   sum dP/du2   = (u2/4 + th - 1/2) M_1 - th/4 M_xi2 - M_x/2 - M_x^2/4
+//   sum dP/dth   = (u2 + 2 th - 1) M_1 + (1/2 - u2/4 - 2 th) M_xi2 + th/4 M_xi2^2
+//                  + M_xi2x/2 - 2 M_x + M_xi2x^2/4 - 3/2 M_x^2.
+// The moments are a constant linear map of the 37 inputs (15 accumulators),
+// which keeps the register footprint small.
 struct EqVjp {
     double sp, sxx, sxz, su2, sth;
 };
 
 __device__ __forceinline__ EqVjp eq_vjp_sums(const double lam[Q], double vx, double vz, double th) {
-    const double u2 = vx * vx + vz * vz;
-    EqVjp r = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // m[p][q]: p powers of xi_x, q of xi_z
+    double m00 = 0, m10 = 0, m01 = 0, m20 = 0, m11 = 0, m02 = 0, m30 = 0, m21 = 0, m12 = 0, m03 = 0;
+    double m40 = 0, m31 = 0, m22 = 0, m13 = 0, m04 = 0;
 #pragma unroll
-    for (int s = 0; s < NSHELL; ++s) {
-        const double xi2 = XI2_SHELL[s];
-        const ShellCoef<double> c = shell_coef<double>(u2, th, xi2);
-        const double a0 = 1.0 + c.a0m1;
-        const double a0_u2 = -0.5 + 0.25 * u2 + 0.25 * th * (4.0 - xi2);
-        const double a0_th = 0.5 * (xi2 - 2.0) + 0.25 * u2 * (4.0 - xi2) +
-                             0.25 * th * (xi2 * xi2 - 8.0 * xi2 + 8.0);
-        const double a1_th = 0.5 * (xi2 - 4.0), a2_th = 0.25 * (xi2 - 6.0);
-        const double w = W_SHELL[s];
-        double sp = 0.0, sxx = 0.0, sxz = 0.0, su2 = 0.0, sth = 0.0;
-#pragma unroll
-        for (int l = 0; l < Q; ++l) {
-            if (SHELL[l] != s) continue;
-            if (l == 0) {   // rest velocity: x = 0, xi = 0
-                sp += lam[0] * a0;
-                su2 += lam[0] * a0_u2;
-                sth += lam[0] * a0_th;
-                continue;
-            }
-            if ((l & 1) == 0) continue;      // -e handled with its +e partner
-            const double cx = R * EX[l], cz = R * EZ[l];
-            const double x = cx * vx + cz * vz, x2 = x * x;
-            const double lp = lam[l] + lam[l + 1], lm = lam[l] - lam[l + 1];
-            // P(+-x) = pe +- po, P'(+-x) = de +- do_, etc.
-            const double pe = a0 + x2 * (c.a2 + x2 * (1.0 / 24.0));
-            const double po = x * (c.a1 + x2 * (1.0 / 6.0));
-            const double de = c.a1 + 0.5 * x2, dodd = x * (2.0 * c.a2 + x2 * (1.0 / 6.0));
-            sp += lp * pe + lm * po;
-            // xi_{l+1} = -xi_l: lam_l P'(x) xi_l + lam_{l+1} P'(-x) (-xi_l)
-            const double dx = lm * de + lp * dodd;
-            sxx += dx * cx;
-            sxz += dx * cz;
-            su2 += lp * (a0_u2 - 0.25 * x2) - lm * 0.5 * x;
-            sth += lp * (a0_th + a2_th * x2) + lm * a1_th * x;
+    for (int l = 0; l < Q; ++l) {
+        const double lw = lam[l] * W[l];
+        const double a = R * EX[l], b = R * EZ[l];
+        m00 += lw;
+        if (EX[l] != 0) {
+            m10 += lw * a;
+            m20 += lw * (a * a);
+            m30 += lw * (a * a * a);
+            m40 += lw * (a * a * a * a);
         }
-        r.sp += w * sp;
-        r.sxx += w * sxx;
-        r.sxz += w * sxz;
-        r.su2 += w * su2;
-        r.sth += w * sth;
+        if (EZ[l] != 0) {
+            m01 += lw * b;
+            m02 += lw * (b * b);
+            m03 += lw * (b * b * b);
+            m04 += lw * (b * b * b * b);
+        }
+        if (EX[l] != 0 && EZ[l] != 0) {
+            m11 += lw * (a * b);
+            m21 += lw * (a * a * b);
+            m12 += lw * (a * b * b);
+            m31 += lw * (a * a * a * b);
+            m22 += lw * (a * a * b * b);
+            m13 += lw * (a * b * b * b);
+        }
     }
+    const double u2 = vx * vx + vz * vz;
+    const double vxx = vx * vx, vxz = vx * vz, vzz = vz * vz;
+    // contracted moments
+    const double Ms = m20 + m02, Mss = m40 + 2.0 * m22 + m04;
+    const double Mx = vx * m10 + vz * m01;
+    const double Msx = vx * (m30 + m12) + vz * (m21 + m03);
+    const double Mxx = vxx * m20 + 2.0 * vxz * m11 + vzz * m02;
+    const double Msxx = vxx * (m40 + m22) + 2.0 * vxz * (m31 + m13) + vzz * (m22 + m04);
+    const double Mx3 = vx * vxx * m30 + 3.0 * vxx * vz * m21 + 3.0 * vx * vzz * m12 + vz * vzz * m03;
+    const double Mx4 = vxx * vxx * m40 + 4.0 * vxx * vxz * m31 + 6.0 * vxx * vzz * m22 +
+                       4.0 * vxz * vzz * m13 + vzz * vzz * m04;
+    const double a0 = 1.0 - 0.5 * u2 - th + 0.125 * u2 * u2 + th * u2 + th * th;
+    const double a1 = 0.5 * th - 0.25 * th * u2 - th * th, a2 = 0.125 * th * th;
+    const double b0 = 1.0 - 0.5 * u2 - 2.0 * th, b1 = 0.5 * th;
+    const double c0 = 0.5 - 0.25 * u2 - 1.5 * th, c1 = 0.25 * th;
+    EqVjp r;
+    r.sp = a0 * m00 + a1 * Ms + a2 * Mss + b0 * Mx + b1 * Msx + c0 * Mxx + c1 * Msxx + Mx3 * (1.0 / 6.0) +
+           Mx4 * (1.0 / 24.0);
+    // x-component: M_i = m10, M_xi2 i = m30 + m12, M_x i = vx m20 + vz m11, ...
+    r.sxx = b0 * m10 + b1 * (m30 + m12) + 2.0 * c0 * (vx * m20 + vz * m11) +
+            2.0 * c1 * (vx * (m40 + m22) + vz * (m31 + m13)) +
+            0.5 * (vxx * m30 + 2.0 * vxz * m21 + vzz * m12) +
+            (vx * vxx * m40 + 3.0 * vxx * vz * m31 + 3.0 * vx * vzz * m22 + vz * vzz * m13) * (1.0 / 6.0);
+    r.sxz = b0 * m01 + b1 * (m21 + m03) + 2.0 * c0 * (vx * m11 + vz * m02) +
+            2.0 * c1 * (vx * (m31 + m13) + vz * (m22 + m04)) +
+            0.5 * (vxx * m21 + 2.0 * vxz * m12 + vzz * m03) +
+            (vx * vxx * m31 + 3.0 * vxx * vz * m22 + 3.0 * vx * vzz * m13 + vz * vzz * m04) * (1.0 / 6.0);
+    r.su2 = (0.25 * u2 + th - 0.5) * m00 - 0.25 * th * Ms - 0.5 * Mx - 0.25 * Mxx;
+    r.sth = (u2 + 2.0 * th - 1.0) * m00 + (0.5 - 0.25 * u2 - 2.0 * th) * Ms + 0.25 * th * Mss + 0.5 * Msx -
+            2.0 * Mx + 0.25 * Msxx - 1.5 * Mxx;
     return r;
 }
 
