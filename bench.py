@@ -72,9 +72,10 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def cpu_baseline(wl, columns=16, steps=8):
+def cpu_baseline(wl, columns=32, min_seconds=10.0, max_steps=64):
     """The oracle on a strip of the same workload: `columns` full-height
-    columns of the lattice, periodic across the strip, `steps` steps."""
+    columns of the lattice, periodic across the strip, stepped until at least
+    `min_seconds` of CPU time (at least 2 steps, at most `max_steps`)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -85,9 +86,12 @@ def cpu_baseline(wl, columns=16, steps=8):
     desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
     f, ghost = O.init_rt3(p_full, desc, m.amp, columns=np.arange(columns))
     p = O.Params(columns, wl.lz, wl.tau, wl.g)
+    steps = 0
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        O.run(f, ghost, p, steps)
+        while steps < max_steps and (steps < 2 or time.perf_counter() - t0 < min_seconds):
+            f = O.step(f, ghost, p)
+            steps += 1
         dt = time.perf_counter() - t0
     return {"value": columns * wl.lz * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
             "kind": "oracle",

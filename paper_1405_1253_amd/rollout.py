@@ -48,6 +48,7 @@ class RolloutConfig:
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
         kw.setdefault("ckpt_every", wl.ckpt_every or 100)
         kw.setdefault("precision", wl.precision)
+        kw.setdefault("adj_precision", wl.adj_precision)
         return cls(wl.lx, wl.lz, wl.tau, wl.g, wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k,
                    modes.phase, wl.steps if nsteps is None else nsteps, **kw)
 

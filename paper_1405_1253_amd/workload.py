@@ -40,6 +40,7 @@ class Workload:
     t_u: float = 0.95
     width: float = 4.0
     ckpt_every: int = 0       # adjoint workloads: state checkpoint interval
+    adj_precision: str = "f64"  # adjoint workloads: "f32" = float adjoint buffers
 
     @property
     def g(self) -> float:
@@ -56,7 +57,8 @@ WORKLOADS = {
         Workload("rt3_4096x12288", 4096, 12288, 1000, "f64", 1405),
         Workload("rt3_4096x12288_f32", 4096, 12288, 20000, "f32dev", 1405),
         Workload("rt3_512x1536_adj", 512, 1536, 2000, "f64", 1253, ckpt_every=100),
-        Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250),
+        Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250,
+                 adj_precision="f32"),
     )
 }
 
