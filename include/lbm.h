@@ -106,14 +106,18 @@ typedef struct lbm_rt3_desc {
     int32_t reserved;      /* 0                                               */
     const int32_t *k;      /* (host) [2][nmodes] integer wavenumbers          */
     const double *phase;   /* (host) [2][nmodes] phases, radians              */
+    double z_lo, z_hi;     /* rest heights (sites above the bottom wall) of the
+                              lower (t_d | t_m) and upper (t_m | t_u) interface;
+                              a negative value selects Lz/3 and 2Lz/3         */
 } lbm_rt3_desc;
 
 /*
  * lbm_init_rt3 -- three-layer hydrostatic initial state and wall table.
  *
  * Sec. I, eq. seteq and the pressure-matching condition; the tanh smoothing
- * of the Fig. 1 caption.  Interface f (0 = lower, at Lz/3; 1 = upper, at
- * 2Lz/3) sits at height
+ * of the Fig. 1 caption.  Interface f (0 = lower, rest height h0_0 = z_lo;
+ * 1 = upper, h0_1 = z_hi; the middle layer of width delta = z_hi - z_lo)
+ * sits at height
  *     h_f(x) = h0_f + sum_j amp[f][j] cos(2 pi k[f][j] (x + 1/2) / Lx + phase[f][j])
  * (sites; site (x, z) has centre z + 1/2), the temperature is
  *     T = t_d + (t_m - t_d) s((z + 1/2 - h_0)/width) + (t_u - t_m) s((z + 1/2 - h_1)/width),
@@ -158,7 +162,7 @@ int lbm_step(const lbm_params *params, const void *ghost, const void *f_in, void
 
 /*
  * lbm_scratch_bytes -- size of the scratch buffer that lbm_moments,
- * lbm_objective and lbm_init_rt3_vjp need (bytes).
+ * lbm_profiles, lbm_objective and lbm_init_rt3_vjp need (bytes).
  * Returns 0 for invalid params.
  */
 size_t lbm_scratch_bytes(const lbm_params *params);
@@ -183,6 +187,24 @@ size_t lbm_scratch_bytes(const lbm_params *params);
  */
 int lbm_moments(const lbm_params *params, const void *f, double *fields, double *tbar,
                 double *sums, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+
+/*
+ * lbm_profiles -- horizontal mean and rms fluctuation profiles of a state.
+ *
+ * Sec. IV (Figs. 8 and 9): for every row z, over the Lx sites of the row,
+ *     prof[0][z] = <T^H>,  prof[1][z] = sqrt(<(T^H - <T^H>)^2>),
+ *     prof[2][z] = <E_k>,  prof[3][z] = sqrt(<(E_k - <E_k>)^2>),
+ * with E_k = rho |u^H|^2 / 2 the kinetic energy density.  The second moments
+ * are accumulated about each row's value at x = 0, so small fluctuations do
+ * not cancel; the order of all sums is fixed (bitwise reproducible).
+ *
+ *   f        (device) state buffer
+ *   prof     (device) double [4][Lz], written
+ *   scratch  (device) at least lbm_scratch_bytes(params) bytes
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_profiles(const lbm_params *params, const void *f, double *prof, void *scratch,
+                 size_t scratch_bytes, lbm_stream_t stream);
 
 /*
  * lbm_objective -- mixing objective of a state and (optionally) its gradient.

@@ -189,7 +189,7 @@ def init_vjp(lam0, p, desc, amp):
     _, _, _, r = lattice()
     lx, lz = p.lx, p.lz
     zc_all = np.arange(-3, lz + 3) + 0.5
-    T_hs = lbm.layer_temperature(zc_all, lz / 3.0, 2.0 * lz / 3.0, desc)
+    T_hs = lbm.layer_temperature(zc_all, *lbm.rest_heights(lz, desc), desc)
     lp_hs = lbm.hydrostatic_log_pressure(T_hs, r, p.g)
     C = 1.0 / (np.exp(lp_hs) / T_hs)[3:3 + lz].mean()
     h0, h1 = lbm.interface_heights(lx, lz, desc, amp)

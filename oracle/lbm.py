@@ -203,6 +203,20 @@ def tbar(TH):
     return TH.mean(axis=0)
 
 
+def profiles(f, p):
+    """Row profiles of Sec. IV (Figs. 8 and 9): mean and rms fluctuation
+    over x of the temperature T^H and of the kinetic energy density
+    E_k = rho |u^H|^2 / 2:  [<T>, sqrt(<(T - <T>)^2>), <E_k>, sqrt(<(E_k - <E_k>)^2>)],
+    each [Lz]."""
+    rho, uH, TH = hydro_fields(f, p)
+    ek = 0.5 * rho * np.sum(uH * uH, axis=-1)
+    out = []
+    for X in (TH, ek):
+        m = X.mean(axis=0)
+        out += [m, np.sqrt(((X - m[None, :]) ** 2).mean(axis=0))]
+    return np.array(out)
+
+
 def tent(b):
     """Tent map of Sec. IV: 2b on (0, 1/2), 2(1 - b) on [1/2, 1), 0 outside.
 
@@ -244,15 +258,25 @@ class RT3:
     width: float        # tanh half-width of the interfaces, in sites
     k: np.ndarray       # [2, nmodes] integer wavenumbers (front 0 lower, 1 upper)
     phase: np.ndarray   # [2, nmodes]
+    z_lo: float = None  # rest height of the lower interface (sites); None: Lz/3
+    z_hi: float = None  # rest height of the upper interface; None: 2 Lz/3
+
+
+def rest_heights(lz, desc):
+    """Rest heights of the two interfaces: the middle layer of Sec. I spans
+    (z_lo, z_hi); by default the three layers are equal thirds."""
+    lo = lz / 3.0 if desc.z_lo is None else float(desc.z_lo)
+    hi = 2.0 * lz / 3.0 if desc.z_hi is None else float(desc.z_hi)
+    return lo, hi
 
 
 def interface_heights(lx, lz, desc, amp, columns=None):
     """Heights (site units, z = 0 at the bottom wall) of the two interfaces
     h_f(x) = h0_f + sum_j amp[f, j] cos(2 pi k[f, j] (x + 1/2) / Lx + phase[f, j]),
-    with h0 = Lz/3 (lower, T_d | T_m) and 2 Lz/3 (upper, T_m | T_u), at every
+    with h0 the rest heights (lower, T_d | T_m, and upper, T_m | T_u), at every
     column or at the given column indices."""
     xc = (np.arange(lx) if columns is None else np.asarray(columns)) + 0.5
-    base = (lz / 3.0, 2.0 * lz / 3.0)
+    base = rest_heights(lz, desc)
     hs = []
     for fr in range(2):
         arg = 2 * np.pi * np.outer(np.asarray(desc.k[fr], float), xc) / lx \
@@ -296,7 +320,7 @@ def init_rt3(p, desc, amp, columns=None):
     lx, lz = p.lx, p.lz
     zc_all = np.arange(-3, lz + 3) + 0.5                 # rows -3 .. Lz+2
     # unperturbed profile (also the walls)
-    T_hs = layer_temperature(zc_all, lz / 3.0, 2.0 * lz / 3.0, desc)
+    T_hs = layer_temperature(zc_all, *rest_heights(lz, desc), desc)
     lp_hs = hydrostatic_log_pressure(T_hs, r, p.g)
     rho_hs = np.exp(lp_hs) / T_hs
     C = 1.0 / rho_hs[3:3 + lz].mean()

@@ -43,7 +43,8 @@ class lbm_rt3_desc(ctypes.Structure):
     _fields_ = [("t_d", ctypes.c_double), ("t_m", ctypes.c_double), ("t_u", ctypes.c_double),
                 ("width", ctypes.c_double), ("nmodes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("k", ctypes.POINTER(ctypes.c_int32)),
-                ("phase", ctypes.POINTER(ctypes.c_double))]
+                ("phase", ctypes.POINTER(ctypes.c_double)), ("z_lo", ctypes.c_double),
+                ("z_hi", ctypes.c_double)]
 
 
 _LIB = None
@@ -74,8 +75,9 @@ def load():
         lib.lbm_adjoint_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP]
         lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP]
+        lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
         for name in ("lbm_init_rt3", "lbm_step", "lbm_moments", "lbm_lattice", "lbm_objective",
-                     "lbm_adjoint_step", "lbm_init_rt3_vjp"):
+                     "lbm_adjoint_step", "lbm_init_rt3_vjp", "lbm_profiles"):
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -115,14 +117,15 @@ def _check(status, where):
 class RT3Desc:
     """Host-side lbm_rt3_desc with the arrays it points to kept alive."""
 
-    def __init__(self, t_d, t_m, t_u, width, k=None, phase=None):
+    def __init__(self, t_d, t_m, t_u, width, k=None, phase=None, z_lo=None, z_hi=None):
         self.k = np.ascontiguousarray(np.zeros((2, 0)) if k is None else k, dtype=np.int32)
         self.phase = np.ascontiguousarray(np.zeros((2, 0)) if phase is None else phase,
                                           dtype=np.float64)
         nmodes = self.k.shape[1] if self.k.ndim == 2 else 0
         self.c = lbm_rt3_desc(t_d, t_m, t_u, width, nmodes, 0,
                               self.k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                              self.phase.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                              self.phase.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              -1.0 if z_lo is None else z_lo, -1.0 if z_hi is None else z_hi)
 
     @property
     def nmodes(self):
@@ -190,3 +193,10 @@ def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):
     st = load().lbm_init_rt3_vjp(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(lam0),
                                  _ptr(d_amp), _ptr(scratch), _nbytes(scratch), _stream(stream))
     _check(st, "lbm_init_rt3_vjp")
+
+
+def lbm_profiles(params, f, prof, scratch, stream=None):
+    """Row means and rms fluctuations of T^H and E_k into prof [4, Lz] (see include/lbm.h)."""
+    st = load().lbm_profiles(ctypes.byref(params), _ptr(f), _ptr(prof), _ptr(scratch),
+                             _nbytes(scratch), _stream(stream))
+    _check(st, "lbm_profiles")

@@ -57,14 +57,22 @@ size_t field_bytes(const lbm_params *p) { return (size_t)4 * p->lx * p->lz * siz
 // Unperturbed column, rows -3 .. Lz+2, on the host: the density
 // normalisation C and the wall rows.  Same construction as the device
 // columns: trapezoid rule for d ln p/dz = -g/T, one row = r length units.
+// Rest heights of the interfaces; a negative entry selects Lz/3 or 2Lz/3.
+void rest_heights(const lbm_params *p, const lbm_rt3_desc *d, double *lo, double *hi) {
+    *lo = d->z_lo < 0.0 ? p->lz / 3.0 : d->z_lo;
+    *hi = d->z_hi < 0.0 ? 2.0 * p->lz / 3.0 : d->z_hi;
+}
+
 void host_profile(const lbm_params *p, const lbm_rt3_desc *d, double *norm, double ghost_rho[6],
                   double ghost_t[6]) {
     const int lz = p->lz, n = lz + 6;
+    double z_lo, z_hi;
+    rest_heights(p, d, &z_lo, &z_hi);
     std::vector<double> T(n), lnp(n);
     for (int i = 0; i < n; ++i) {
         const double zc = (double)(i - 3) + 0.5;
-        const double s0 = 0.5 * (1.0 + tanh((zc - lz / 3.0) / d->width));
-        const double s1 = 0.5 * (1.0 + tanh((zc - 2.0 * lz / 3.0) / d->width));
+        const double s0 = 0.5 * (1.0 + tanh((zc - z_lo) / d->width));
+        const double s1 = 0.5 * (1.0 + tanh((zc - z_hi) / d->width));
         T[i] = d->t_d + (d->t_m - d->t_d) * s0 + (d->t_u - d->t_m) * s1;
     }
     lnp[0] = 0.0;
@@ -91,6 +99,7 @@ int check_desc(const lbm_rt3_desc *d, const double *amp) {
         return LBM_EINVAL;
     for (int i = 0; i < 2 * d->nmodes; ++i)
         if (!isfinite(d->phase[i])) return LBM_EINVAL;
+    if (!isfinite(d->z_lo) || !isfinite(d->z_hi)) return LBM_EINVAL;
     return LBM_OK;
 }
 
@@ -136,7 +145,31 @@ size_t lbm_scratch_bytes(const lbm_params *p) {
     size_t b = lbm::moments_scratch_bytes(p->lx, p->lz);
     if (lbm::objective_scratch_bytes(p->lx, p->lz) > b) b = lbm::objective_scratch_bytes(p->lx, p->lz);
     if (vjp_scratch_bytes(p->lx) > b) b = vjp_scratch_bytes(p->lx);
+    if (lbm::profiles_scratch_bytes(p->lx, p->lz) > b) b = lbm::profiles_scratch_bytes(p->lx, p->lz);
     return b;
+}
+
+int lbm_profiles(const lbm_params *p, const void *f, double *prof, void *scratch, size_t scratch_bytes,
+                 lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!f || !prof) return LBM_EINVAL;
+    if (!aligned(f, 16) || !aligned(prof, 8) || !aligned(scratch, 256)) return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const size_t need = lbm::profiles_scratch_bytes(p->lx, p->lz);
+    if (!scratch || scratch_bytes < need) return LBM_ESCRATCH;
+    const size_t sb = state_bytes(p), pb = (size_t)4 * p->lz * sizeof(double);
+    if (overlap(prof, pb, f, sb) || overlap(scratch, need, f, sb) || overlap(scratch, need, prof, pb))
+        return LBM_EALIAS;
+    lbm::ProfileArgs a;
+    a.f = f;
+    a.prof = prof;
+    a.scratch = scratch;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.g = p->g;
+    return hip_status(lbm::launch_profiles(a, p->precision, (hipStream_t)stream));
 }
 
 int lbm_step(const lbm_params *p, const void *ghost, const void *f_in, void *f_out,
@@ -226,6 +259,7 @@ int lbm_init_rt3(const lbm_params *p, const lbm_rt3_desc *d, const double *amp, 
     a.t_m = d->t_m;
     a.t_u = d->t_u;
     a.width = d->width;
+    rest_heights(p, d, &a.z_lo, &a.z_hi);
     for (int f = 0; f < 2; ++f)
         for (int j = 0; j < d->nmodes; ++j) {
             a.k[f][j] = d->k[f * d->nmodes + j];
@@ -327,6 +361,7 @@ int lbm_init_rt3_vjp(const lbm_params *p, const lbm_rt3_desc *d, const double *a
     a.t_m = d->t_m;
     a.t_u = d->t_u;
     a.width = d->width;
+    rest_heights(p, d, &a.z_lo, &a.z_hi);
     for (int f = 0; f < 2; ++f)
         for (int j = 0; j < d->nmodes; ++j) {
             a.k[f][j] = d->k[f * d->nmodes + j];

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(BLOCK) void init_columns(InitArgs a) {
     const size_t N = (size_t)a.lx * (size_t)a.lz;
 
     if (tid < 2) {
-        double h = (tid == 0 ? 1.0 : 2.0) * (double)a.lz / 3.0;
+        double h = tid == 0 ? a.z_lo : a.z_hi;
         for (int j = 0; j < a.nmodes; ++j)
             h += a.amp[tid * a.nmodes + j] *
                  cos(2.0 * M_PI * (double)a.k[tid][j] * ((double)x + 0.5) / (double)a.lx +

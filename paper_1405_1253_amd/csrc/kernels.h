@@ -34,6 +34,16 @@ struct MomentArgs {
 size_t moments_scratch_bytes(int lx, int lz);
 hipError_t launch_moments(const MomentArgs &a, int precision, hipStream_t s);
 
+struct ProfileArgs {
+    const void *f;
+    double *prof;        // [4][lz]
+    void *scratch;
+    int lx, lz;
+    double g;
+};
+size_t profiles_scratch_bytes(int lx, int lz);
+hipError_t launch_profiles(const ProfileArgs &a, int precision, hipStream_t s);
+
 constexpr int MAX_MODES = 32;
 struct InitArgs {
     void *f_out;
@@ -41,6 +51,7 @@ struct InitArgs {
     const double *amp;   // device [2][nmodes]
     int lx, lz, nmodes;
     double g, t_d, t_m, t_u, width;
+    double z_lo, z_hi;   // rest heights of the two interfaces (sites)
     double norm;         // C: density = C p / T
     double ghost_rho[6], ghost_t[6];   // rows -1,-2,-3 then Lz, Lz+1, Lz+2
     int k[2][MAX_MODES];
@@ -78,6 +89,7 @@ struct InitVjpArgs {
     double *dh;            // scratch [2][lx]
     int lx, lz, nmodes;
     double g, t_d, t_m, t_u, width, norm;
+    double z_lo, z_hi;
     int k[2][MAX_MODES];
     double phase[2][MAX_MODES];
 };

@@ -131,4 +131,95 @@ hipError_t launch_moments(const MomentArgs &a, int precision, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// row profiles: mean and rms fluctuation of T^H and E_k = rho |u^H|^2 / 2
+// ---------------------------------------------------------------------------
+template <int PREC>
+__device__ __forceinline__ void site_th_ek(const void *fp, size_t N, size_t site, double g, double &th,
+                                           double &ek) {
+    using E = typename std::conditional<PREC == P_F64, double, float>::type;
+    const E *f = static_cast<const E *>(fp);
+    double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        const double v = (double)f[(size_t)l * N + site];
+        s0 += v;
+        if (EX[l] != 0) sx += EX[l] * v;
+        if (EZ[l] != 0) sz += EZ[l] * v;
+        if (SHELL[l] != 0) s2 += (EX[l] * EX[l] + EZ[l] * EZ[l]) * v;
+    }
+    const double rho = (PREC == P_F64) ? s0 : 1.0 + s0;
+    const double e2 = (PREC == P_F64) ? R2 * s2 : D + R2 * s2;
+    const double inv = 1.0 / rho;
+    const double ux = R * sx * inv, uz = R * sz * inv;
+    th = (e2 * inv - ux * ux - uz * uz) / D + g * g / (4.0 * D);
+    const double uhz = uz + 0.5 * g;
+    ek = 0.5 * rho * (ux * ux + uhz * uhz);
+}
+
+size_t profiles_scratch_bytes(int lx, int lz) {
+    const size_t nxc = (size_t)(lx + XC - 1) / XC;
+    return align256(4 * nxc * (size_t)lz * sizeof(double));
+}
+
+// pass 1: strip partials of (T - T0), (T - T0)^2, (E - E0), (E - E0)^2 with
+// T0, E0 the row's values at x = 0
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void profiles_pass1(ProfileArgs a, int nzb, int nxc) {
+    const int zb = blockIdx.x % nzb, xc = blockIdx.x / nzb;
+    const int z = zb * BLOCK + threadIdx.x;
+    if (z >= a.lz) return;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    double t0, e0;
+    site_th_ek<PREC>(a.f, N, (size_t)z, a.g, t0, e0);
+    double st = 0.0, stt = 0.0, se = 0.0, see = 0.0;
+    const int x1 = min(xc * XC + XC, a.lx);
+    for (int x = xc * XC; x < x1; ++x) {
+        double th, ek;
+        site_th_ek<PREC>(a.f, N, (size_t)x * a.lz + z, a.g, th, ek);
+        const double dt = th - t0, de = ek - e0;
+        st += dt;
+        stt += dt * dt;
+        se += de;
+        see += de * de;
+    }
+    double *part = static_cast<double *>(a.scratch);
+    const size_t stride = (size_t)nxc * a.lz, o = (size_t)xc * a.lz + z;
+    part[o] = st;
+    part[stride + o] = stt;
+    part[2 * stride + o] = se;
+    part[3 * stride + o] = see;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(BLOCK) void profiles_pass2(ProfileArgs a, int nxc) {
+    const int z = blockIdx.x * BLOCK + threadIdx.x;
+    if (z >= a.lz) return;
+    const double *part = static_cast<const double *>(a.scratch);
+    const size_t stride = (size_t)nxc * a.lz;
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < nxc; ++c)
+        for (int k = 0; k < 4; ++k) m[k] += part[k * stride + (size_t)c * a.lz + z];
+    double t0, e0;
+    site_th_ek<PREC>(a.f, (size_t)a.lx * (size_t)a.lz, (size_t)z, a.g, t0, e0);
+    const double inv = 1.0 / (double)a.lx;
+    const double mt = m[0] * inv, me = m[2] * inv;
+    a.prof[z] = t0 + mt;
+    a.prof[a.lz + z] = sqrt(fmax(m[1] * inv - mt * mt, 0.0));
+    a.prof[2 * a.lz + z] = e0 + me;
+    a.prof[3 * a.lz + z] = sqrt(fmax(m[3] * inv - me * me, 0.0));
+}
+
+hipError_t launch_profiles(const ProfileArgs &a, int precision, hipStream_t s) {
+    const int nxc = (a.lx + XC - 1) / XC, nzb = (a.lz + BLOCK - 1) / BLOCK;
+    if (precision == P_F64) {
+        hipLaunchKernelGGL(profiles_pass1<P_F64>, dim3(nzb * nxc), dim3(BLOCK), 0, s, a, nzb, nxc);
+        hipLaunchKernelGGL(profiles_pass2<P_F64>, dim3(nzb), dim3(BLOCK), 0, s, a, nxc);
+    } else {
+        hipLaunchKernelGGL(profiles_pass1<P_F32_DEV>, dim3(nzb * nxc), dim3(BLOCK), 0, s, a, nzb, nxc);
+        hipLaunchKernelGGL(profiles_pass2<P_F32_DEV>, dim3(nzb), dim3(BLOCK), 0, s, a, nxc);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace lbm

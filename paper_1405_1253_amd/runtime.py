@@ -35,14 +35,17 @@ class Lattice:
         lat = cls(wl.lx, wl.lz, wl.tau, wl.g, precision=wl.precision, device=device, **kw)
         modes = modes if modes is not None else draw_modes(wl.seed)
         a = modes.amp if amp is None else amp
-        lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k, modes.phase, a)
+        lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k, modes.phase, a, wl.z_lo, wl.z_hi)
+        if wl.t_m_diag is not None:
+            lat.diag_desc = abi.RT3Desc(wl.t_d, wl.t_m_diag, wl.t_u, wl.width)
         return lat
 
-    def init_rt3(self, t_d, t_m, t_u, width, k, phase, amp):
+    def init_rt3(self, t_d, t_m, t_u, width, k, phase, amp, z_lo=None, z_hi=None):
         if not torch.is_tensor(amp):
             amp = torch.as_tensor(np.asarray(amp, dtype=np.float64), device=self.device)
         amp = amp.to(device=self.device, dtype=torch.float64).contiguous()
-        self.desc = abi.RT3Desc(t_d, t_m, t_u, width, k, phase)
+        self.desc = abi.RT3Desc(t_d, t_m, t_u, width, k, phase, z_lo, z_hi)
+        self.diag_desc = self.desc     # temperatures of the tent-map diagnostics
         abi.lbm_init_rt3(self.params, self.desc, amp, self.buf[0], self.ghost)
         self.cur = 0
         self.steps_done = 0
@@ -76,6 +79,18 @@ class Lattice:
         abi.lbm_moments(self.params, self.state, tbar=out, scratch=self.scratch)
         return out
 
+    def profiles(self):
+        """[4, Lz]: mean and rms fluctuation over x of T^H and of E_k."""
+        out = torch.empty((4, self.lz), dtype=torch.float64, device=self.device)
+        abi.lbm_profiles(self.params, self.state, out, self.scratch)
+        return out
+
+    def objective(self, wk=1.0, wl=1.0):
+        """[3]: J = wk KE + wl (L_u + L_d), KE, L_u + L_d of the current state."""
+        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        abi.lbm_objective(self.params, self.diag_desc, self.state, wk, wl, out, None, self.scratch)
+        return out
+
     def sums(self, check=True):
         out = torch.empty(4, dtype=torch.float64, device=self.device)
         abi.lbm_moments(self.params, self.state, sums=out, scratch=self.scratch)
@@ -84,6 +99,32 @@ class Lattice:
             if not torch.isfinite(host).all():
                 raise FloatingPointError(f"non-finite global sums {host.tolist()}: state diverged")
         return out
+
+    # ---- checkpoint / restore ---------------------------------------------
+    def state_dict(self):
+        """Everything needed to continue the run bitwise: state, wall table,
+        parameters and step count (host tensors)."""
+        return {"lx": self.lx, "lz": self.lz, "tau": self.tau, "g": self.g,
+                "precision": self.precision, "flags": int(self.params.flags),
+                "steps_done": self.steps_done, "state": self.state.cpu(),
+                "ghost": self.ghost.cpu()}
+
+    def save(self, path):
+        torch.save(self.state_dict(), path)
+
+    @classmethod
+    def from_state_dict(cls, d, device="cuda"):
+        lat = cls(d["lx"], d["lz"], d["tau"], d["g"], precision=d["precision"],
+                  flags=d["flags"], device=device)
+        lat.buf[0].copy_(d["state"])
+        lat.ghost.copy_(d["ghost"])
+        lat.cur = 0
+        lat.steps_done = d["steps_done"]
+        return lat
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        return cls.from_state_dict(torch.load(path, weights_only=True), device=device)
 
     def populations(self):
         """Full populations f_l as float64 (adds the weights back in FP32 mode)."""

@@ -12,6 +12,8 @@ Table II, scaled to the measured shapes):
   rt3_4096x12288_f32 the same lattice with FP32 deviation storage
   rt3_512x1536_adj   FP64 with 32 interface modes differentiated
   rt3_2048x6144_adj  FP32 storage forward + adjoint
+  rt3_2400x6144_paper / rt2_2400x6144_paper
+                     the double- and single-front runs of Sec. IV (Table II)
 
 Physics common to all: tau = 0.7, temperatures 1.05 / 1.00 / 0.95 (bottom,
 middle, top) in equal thirds, tanh half-width 4 sites, 16 Fourier modes per
@@ -41,10 +43,19 @@ class Workload:
     width: float = 4.0
     ckpt_every: int = 0       # adjoint workloads: state checkpoint interval
     adj_precision: str = "f64"  # adjoint workloads: "f32" = float adjoint buffers
+    z_lo: float = None        # interface rest heights (sites); None: Lz/3, 2 Lz/3
+    z_hi: float = None
+    g_override: float = None  # gravity when not scaled with Lz
+    t_m_diag: float = None    # middle temperature of the tent-map diagnostics
+                              # (the single-front run's "virtual" T_m)
 
     @property
     def g(self) -> float:
-        return 1e-4 * 384.0 / self.lz
+        return self.g_override if self.g_override is not None else 1e-4 * 384.0 / self.lz
+
+    @property
+    def atwood(self) -> float:
+        return (self.t_d - self.t_u) / (self.t_d + self.t_u)
 
     @property
     def sites(self) -> int:
@@ -59,6 +70,15 @@ WORKLOADS = {
         Workload("rt3_512x1536_adj", 512, 1536, 2000, "f64", 1253, ckpt_every=100),
         Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250,
                  adj_precision="f32"),
+        # The runs of Sec. IV, Table II: 2400 x 6144, g = 1.5e-5, T 1.025/1/0.975,
+        # a middle layer delta = 500 for the double front; Ra = 1e10 at Pr = 1
+        # gives nu = sqrt(dT Lz^3 g / Ra) = 5.46e-3 with Lz in length units.
+        Workload("rt3_2400x6144_paper", 2400, 6144, 350000, "f32dev", 1405, tau=0.50546,
+                 t_d=1.025, t_m=1.0, t_u=0.975, z_lo=3072 - 250, z_hi=3072 + 250,
+                 g_override=1.5e-5),
+        Workload("rt2_2400x6144_paper", 2400, 6144, 350000, "f32dev", 1405, tau=0.50546,
+                 t_d=1.025, t_m=1.025, t_u=0.975, z_lo=1536, z_hi=3072, g_override=1.5e-5,
+                 t_m_diag=1.0),
     )
 }
 

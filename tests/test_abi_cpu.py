@@ -97,14 +97,17 @@ def test_moments_and_init_reject_bad_arguments(abi):
     ph = np.zeros((2, 40))
     desc = abi.lbm_rt3_desc(1.05, 1.0, 0.95, 4.0, 40, 0,
                             k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                            ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                            ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), -1.0, -1.0)
     assert lib.lbm_init_rt3(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 3 << 30, None) == -1
     desc.nmodes = 16
     desc.width = 0.0
     assert lib.lbm_init_rt3(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 3 << 30, None) == -1
     desc.width = 4.0
+    desc.z_lo = float("nan")
+    assert lib.lbm_init_rt3(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 3 << 30, None) == -1
+    desc.z_lo = -1.0
     # objective needs t_d > t_m > t_u and scratch; adjoint needs moments unless NO_COLLIDE
-    bad = abi.lbm_rt3_desc(0.95, 1.0, 1.05, 4.0, 0, 0, None, None)
+    bad = abi.lbm_rt3_desc(0.95, 1.0, 1.05, 4.0, 0, 0, None, None, -1.0, -1.0)
     assert lib.lbm_objective(ctypes.byref(p), ctypes.byref(bad), 1 << 30, 1.0, 1.0, 1 << 20, None,
                              3 << 30, need, None) == -1
     assert lib.lbm_objective(ctypes.byref(p), ctypes.byref(desc), 1 << 30, 1.0, 1.0, 1 << 20, None,

@@ -9,6 +9,7 @@
 * The tent-map mixing length of Sec. IV on a linear ramp over W rows is W/2.
 """
 import numpy as np
+import pytest
 
 from oracle import lattice as L
 from oracle import lbm
@@ -23,16 +24,21 @@ def _desc(width=4.0, t=(1.05, 1.0, 0.95), k=None, phase=None):
     return lbm.RT3(t[0], t[1], t[2], width, k, phase)
 
 
-def test_init_sharp_limit_closed_form():
-    lx, lz, g = 4, 48, 2e-3
+@pytest.mark.parametrize("lz,heights", [(48, None), (60, (27, 33)), (60, (10, 50))])
+def test_init_sharp_limit_closed_form(lz, heights):
+    lx, g = 4, 2e-3
     Td, Tm, Tu = 1.05, 1.0, 0.95
     _, _, _, r = L.lattice()
     p = lbm.Params(lx, lz, 0.7, g)
-    f0, ghost = lbm.init_rt3(p, _desc(width=1e-3), np.zeros((2, 16)))
+    desc = _desc(width=1e-3)
+    if heights is not None:
+        desc.z_lo, desc.z_hi = heights
+    f0, ghost = lbm.init_rt3(p, desc, np.zeros((2, 16)))
     rho, uH, TH = lbm.hydro_fields(f0, p)
     # paper's piecewise form, z in length units (one row = r), continuous p
     z = r * (np.arange(lz) + 0.5)
-    z1, z2 = r * lz / 3, r * 2 * lz / 3
+    h1, h2 = heights if heights is not None else (lz / 3, 2 * lz / 3)
+    z1, z2 = r * h1, r * h2
     p1 = np.exp(-g * z1 / Td)                   # pressure at the lower interface
     p2 = p1 * np.exp(-g * (z2 - z1) / Tm)       # ... at the upper interface
     pres = np.where(z < z1, np.exp(-g * z / Td),
@@ -44,7 +50,8 @@ def test_init_sharp_limit_closed_form():
     assert np.allclose(TH, T[None, :], rtol=1e-14, atol=0)
     assert np.allclose(rho, want[None, :], rtol=1e-13, atol=0)
     # density increases upward across both interfaces (unstable stack)
-    assert rho[0, lz // 3] > rho[0, lz // 3 - 1] and rho[0, 2 * lz // 3] > rho[0, 2 * lz // 3 - 1]
+    i1, i2 = int(h1), int(h2)
+    assert rho[0, i1] > rho[0, i1 - 1] and rho[0, i2] > rho[0, i2 - 1]
 
 
 def test_init_fields_are_prescribed():
@@ -94,3 +101,25 @@ def test_global_sums_consistent_with_moments():
     assert np.isclose(s[0], rho.sum(), rtol=1e-14)
     assert np.allclose(s[1:3], (rho[..., None] * u).sum((0, 1)), rtol=1e-13)
     assert np.isclose(s[3], 0.5 * (rho * ((u ** 2).sum(-1) + 2 * T)).sum(), rtol=1e-13)
+
+
+def test_profiles_closed_forms():
+    """Mean/rms of T^H and E_k for fields built with known row statistics:
+    T^H = 1 + eps s(z) cos(theta), u^H = (a cos(theta), 0) with theta the
+    column angle, give <T> = 1, rms T = eps |s| / sqrt(2), <E_k> = rho a^2 / 4,
+    rms E_k = rho a^2 / (4 sqrt 2)."""
+    lx, lz, g = 16, 10, 1e-3
+    p = lbm.Params(lx, lz, 0.7, g)
+    th = 2 * np.pi * (np.arange(lx) + 0.5) / lx
+    s = np.linspace(-1, 1, lz)
+    eps, a, rho0 = 0.01, 0.02, 1.1
+    TH = 1 + eps * np.outer(np.cos(th), s)
+    uH = np.zeros((lx, lz, 2))
+    uH[..., 0] = a * np.cos(th)[:, None]
+    ustar = uH + 0.5 * np.array([0.0, -g])
+    f = lbm.equilibrium(np.full((lx, lz), rho0), ustar, TH - g ** 2 / 8)
+    prof = lbm.profiles(f, p)
+    assert np.allclose(prof[0], 1.0, atol=1e-14)
+    assert np.allclose(prof[1], eps * np.abs(s) / np.sqrt(2), atol=1e-14)
+    assert np.allclose(prof[2], rho0 * a * a / 4, rtol=1e-12)
+    assert np.allclose(prof[3], rho0 * a * a / (4 * np.sqrt(2)), rtol=1e-12)
