@@ -55,6 +55,10 @@ def load():
     """Load liblbm.so (once).  Raises if it has not been built."""
     global _LIB
     if _LIB is None:
+        # torch ships its own HIP runtime; loading it first makes liblbm.so
+        # bind to that same runtime (one runtime per process shares the
+        # device, the streams and the memory torch allocates)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1405_1253_amd.build` (no CPU fallback exists)")
