@@ -1,0 +1,101 @@
+"""FP32 deviation storage against FP64 on the same workload.
+
+    python -m paper_1405_1253_amd.precision fields   [--steps 20000]
+    python -m paper_1405_1253_amd.precision gradient [--steps 5000]
+
+fields:   the 4096 x 12288 three-layer workload is run in FP64 and in FP32
+          deviation storage for the same number of steps; the renormalised
+          fields (rho, u^H_x, u^H_z, T^H) are compared site by site (max and
+          RMS absolute error per field, and the max relative error of rho and
+          T) and the mixing lengths L_u + L_d and KE of both runs are printed.
+gradient: dJ/d amp of the 2048 x 6144 rollout with FP32 storage and float
+          adjoint buffers against the same rollout in FP64 throughout.
+Each mode prints one JSON line.  All arithmetic runs in the library's kernels;
+differences are reduced on the device with torch.
+"""
+import argparse
+import json
+import sys
+import time
+
+import torch
+
+
+def _field_errors(a, b):
+    names = ("rho", "u_x", "u_z", "T")
+    out = {}
+    for i, n in enumerate(names):
+        d = (a[i] - b[i]).abs()
+        out[n] = {"max_abs": float(d.max()), "rms": float(d.pow(2).mean().sqrt())}
+        if n in ("rho", "T"):
+            out[n]["max_rel"] = float((d / b[i].abs()).max())
+    return out
+
+
+def fields(steps):
+    from .runtime import Lattice
+    from .workload import WORKLOADS
+    res = {"mode": "fields", "steps": steps}
+    t0 = time.perf_counter()
+    lat64 = Lattice.from_workload(WORKLOADS["rt3_4096x12288"])
+    lat32 = Lattice.from_workload(WORKLOADS["rt3_4096x12288_f32"])
+    done = 0
+    while done < steps:
+        n = min(2000, steps - done)
+        lat64.step(n)
+        lat32.step(n)
+        done += n
+        torch.cuda.synchronize()
+        print(f"step {done}: {time.perf_counter() - t0:.0f} s", flush=True)
+    lat64.sums()
+    lat32.sums()
+    f64 = lat64.fields()
+    f32 = lat32.fields()
+    res["errors"] = _field_errors(f32, f64)
+    j64 = lat64.objective().cpu().tolist()
+    j32 = lat32.objective().cpu().tolist()
+    res["mixing_length_f64"], res["mixing_length_f32"] = j64[2], j32[2]
+    res["ke_f64"], res["ke_f32"] = j64[1], j32[1]
+    res["seconds"] = time.perf_counter() - t0
+    return res
+
+
+def gradient(steps):
+    from .rollout import Rollout, RolloutConfig
+    from .workload import WORKLOADS, draw_modes
+    wl = WORKLOADS["rt3_2048x6144_adj"]
+    m = draw_modes(wl.seed)
+    amp = torch.as_tensor(m.amp, device="cuda")
+    grads = {}
+    t0 = time.perf_counter()
+    for prec, adj in (("f32dev", "f32"), ("f64", "f64")):
+        r = Rollout(RolloutConfig.from_workload(wl, m, nsteps=steps, precision=prec, adj_precision=adj,
+                                                moment_budget_bytes=40 << 30))
+        J = r.forward(amp)[0].item()
+        grads[prec] = (J, r.backward())
+        del r
+        torch.cuda.empty_cache()
+        print(f"{prec} rollout done: {time.perf_counter() - t0:.0f} s", flush=True)
+    (J32, g32), (J64, g64) = grads["f32dev"], grads["f64"]
+    err = (g32 - g64).abs()
+    return {"mode": "gradient", "steps": steps, "J_f64": J64, "J_f32": J32,
+            "J_rel_err": abs(J32 / J64 - 1), "grad_max_abs_err": float(err.max()),
+            "grad_max_err_over_max_grad": float(err.max() / g64.abs().max()),
+            "grad_rms_rel_err": float((err.pow(2).mean() / g64.pow(2).mean()).sqrt()),
+            "seconds": time.perf_counter() - t0}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=("fields", "gradient"))
+    ap.add_argument("--steps", type=int, default=None)
+    a = ap.parse_args(argv)
+    if a.mode == "fields":
+        out = fields(a.steps or 20000)
+    else:
+        out = gradient(a.steps or 5000)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
