@@ -17,9 +17,12 @@ One step back:
     dJ/dg_t,l = (1 - omega) lam_t,l + sum_k mu_k dm_k/dg_l,
     mu_k = omega * sum_l lam_t,l dF_l/dm_k,
     dm/dg_l = (1, (xi_l - u)/rho, (|xi_l - u|^2 - D T)/(D rho)),
-    lam_{t-1,l}(y) = dJ/dg_t,l(y + e_l)   (zero where y + e_l is outside the
-                                           wall-bounded rows: those g entries
-                                           come from the constant wall table)
+    lam_{t-1,l}(y) = dJ/dg_t,l(y + e_l)   where y + e_l is inside the
+                                           wall-bounded rows; beyond a wall it
+                                           is zero for the Dirichlet wall (a
+                                           constant table) and the ghost site's
+                                           summed sensitivity for the diffuse
+                                           wall (see ``pull_transpose``)
 """
 import numpy as np
 
@@ -128,20 +131,44 @@ def moments_vjp(f, g_rho, g_u, g_T):
             + g_T[None] * (cx * cx + cz * cz - D * T[None]) / (D * rho[None]))
 
 
-def pull_transpose(G, p):
+def pull_transpose(G, p, ghost=None):
     """Adjoint of ``lbm.pull`` with respect to its state argument:
-    out_l(y) = G_l(y + e_l), zero where y + e_l leaves the wall-bounded rows."""
+    out_l(y) = G_l(y + e_l) where y + e_l lies inside the wall-bounded rows.
+
+    Where y + e_l is a ghost site: zero for the Dirichlet wall (the table is
+    constant); for the diffuse wall the ghost site's emitted populations are
+    c_m * M with M the sum of the populations that streamed into it, so every
+    one of those receives A = sum_m c_m G_m(ghost site + e_m) over the m that
+    point back into the lattice (``lbm.wall_emission`` gives c from ``ghost``).
+    """
     E, _, _, _ = lattice()
     out = np.empty_like(G)
     lz = G.shape[2]
+    diffuse = not p.periodic_z and p.wall == "diffuse"
+    if diffuse:
+        c = lbm.wall_emission(ghost, lz)
+        A = np.zeros((2, 3, G.shape[1]), dtype=G.dtype)
+        for side in range(2):
+            for i in range(3):
+                k = lbm.ghost_row(side, i, lz)
+                for m in range(G.shape[0]):
+                    ex, ez = int(E[m, 0]), int(E[m, 1])
+                    if 0 <= k + ez < lz:
+                        A[side, i] += c[side, i, m] * np.roll(G[m, :, k + ez], -ex)
     for l in range(G.shape[0]):
         ex, ez = int(E[l, 0]), int(E[l, 1])
         out[l] = np.roll(G[l], shift=(-ex, -ez), axis=(0, 1))
         if p.periodic_z:
             continue
         for y in range(lz):
-            if not 0 <= y + ez < lz:
+            k = y + ez
+            if 0 <= k < lz:
+                continue
+            if not diffuse:
                 out[l, :, y] = 0.0
+            else:
+                side, i = (0, -1 - k) if k < 0 else (1, k - lz)
+                out[l, :, y] = np.roll(A[side, i], -ex)   # ghost site column x + e_lx
     return out
 
 
@@ -149,14 +176,14 @@ def step_vjp(lam, f_prev, ghost, p):
     """lam_{t-1} = (d step / d f*_{t-1})^T lam_t for the step from f_prev."""
     g = lbm.pull(f_prev, ghost, p)
     if p.no_collide:
-        return pull_transpose(lam, p)
+        return pull_transpose(lam, p, ghost)
     om = 1.0 / p.tau
     rho, u, T = lbm.moments(g)
     v, Teq = lbm.shifted_state(u, T, p)
     g_rho, g_v, g_T = equilibrium_vjp(lam, rho, v, Teq)
     # v = u + tau g_vec and Teq = T + const: d/du = d/dv, d/dT = d/dTeq
     G = (1.0 - om) * lam + om * moments_vjp(g, g_rho, g_v, g_T)
-    return pull_transpose(G, p)
+    return pull_transpose(G, p, ghost)
 
 
 def objective_vjp(f, p, Tu, Tm, Td, wk=1.0, wl=1.0):

@@ -12,9 +12,15 @@ Conventions (readings of the paper where it is silent):
   units, because the populations travel xi_l dt = r e_l per step;
 * arrays of populations are laid out [37, Lx, Lz] (z fastest) and the stored
   state between steps is the post-collision population f*;
-* walls: a population that would be pulled from a row outside [0, Lz) is taken
-  from a constant table ghost[2, 3, 37]: ghost[0, i] is row -1-i below the
-  bottom wall, ghost[1, i] is row Lz+i above the top wall.
+* walls: a population that would be pulled from a row outside [0, Lz) comes
+  from a ghost site three rows deep past each wall; ghost[2, 3, 37] is the
+  wall table, ghost[0, i] for row -1-i below the bottom wall, ghost[1, i] for
+  row Lz+i above the top wall.  Two wall rules (Sec. III.B step bc, which the
+  paper describes only as adjusting rows 0..2 and Lz-3..Lz-1 at rigid walls):
+  "dirichlet" takes the ghost populations from the table as they stand;
+  "diffuse" (mass-conserving diffuse reflection) gives each ghost site the
+  distribution shape of its table row, scaled so that it returns to the
+  lattice exactly the mass that streamed into it in the same step.
 """
 from dataclasses import dataclass
 
@@ -31,6 +37,7 @@ class Params:
     g: float
     periodic_z: bool = False   # test mode: no walls, z wraps like x
     no_collide: bool = False   # test mode: streaming (and walls) only
+    wall: str = "dirichlet"    # "dirichlet" or "diffuse" (see module notes)
 
 
 # --------------------------------------------------------------------------
@@ -126,15 +133,69 @@ def shifted_state(u, T, p):
 # Streaming, walls, collision (Sec. III.A eq. LBE; Sec. III.B)
 # --------------------------------------------------------------------------
 
+def ghost_row(side, i, lz):
+    """Row index of ghost row i on a side (0: below the bottom wall, 1: above
+    the top wall)."""
+    return -1 - i if side == 0 else lz + i
+
+
+def wall_masses(f, lz):
+    """Mass that streams out of the lattice into each ghost site in one pull.
+
+    M[side, i, x] for the ghost site (x, ghost_row(side, i)): the sum over l of
+    f_l(x - e_lx, k - e_lz) over the l whose source row k - e_lz lies inside
+    [0, Lz), i.e. every population leaving the lattice that would land there.
+    """
+    E, _, _, _ = lattice()
+    M = np.zeros((2, 3, f.shape[1]), dtype=f.dtype)
+    for side in range(2):
+        for i in range(3):
+            k = ghost_row(side, i, lz)
+            for l in range(f.shape[0]):
+                ex, ez = int(E[l, 0]), int(E[l, 1])
+                if 0 <= k - ez < lz:
+                    M[side, i] += np.roll(f[l, :, k - ez], ex)
+    return M
+
+
+def wall_emission(ghost, lz):
+    """Emission shares c[side, i, l] of the diffuse wall: the table row's
+    populations that point back into the lattice (k + e_lz inside [0, Lz)),
+    normalised to sum to one over those l; zero for the other l."""
+    E, _, _, _ = lattice()
+    c = np.zeros((2, 3, E.shape[0]))
+    for side in range(2):
+        for i in range(3):
+            k = ghost_row(side, i, lz)
+            into = np.array([0 <= k + int(E[l, 1]) < lz for l in range(E.shape[0])])
+            c[side, i, into] = ghost[side, i, into] / ghost[side, i, into].sum()
+    return c
+
+
 def pull(f, ghost, p):
     """Pull streaming: out_l(x, z) = f_l(x - e_lx mod Lx, z - e_lz).
 
-    Sources below row 0 or above row Lz-1 come from the wall table ``ghost``
-    (walls in z), unless ``p.periodic_z`` (then z wraps as well).
+    Sources below row 0 or above row Lz-1 are ghost sites (walls in z), unless
+    ``p.periodic_z`` (then z wraps as well).  With ``p.wall == "dirichlet"`` a
+    ghost site holds its table row; with ``"diffuse"`` it holds
+    c_l * M, the table row's shape (``wall_emission``) times the mass M that
+    streamed into that ghost site from f (``wall_masses``).
     """
     E, _, _, _ = lattice()
     out = np.empty_like(f)
     lz = f.shape[2]
+    if not p.periodic_z and p.wall == "diffuse":
+        M = wall_masses(f, lz)
+        c = wall_emission(ghost, lz)
+    elif not p.periodic_z and p.wall != "dirichlet":
+        raise ValueError(f"unknown wall rule {p.wall!r}")
+
+    def ghost_value(side, i, l, ex):
+        if p.wall == "diffuse":
+            # the ghost site of column x sits at x - e_lx
+            return c[side, i, l] * np.roll(M[side, i], ex)
+        return ghost[side, i, l]
+
     for l in range(f.shape[0]):
         ex, ez = int(E[l, 0]), int(E[l, 1])
         out[l] = np.roll(f[l], shift=(ex, ez), axis=(0, 1))
@@ -142,10 +203,10 @@ def pull(f, ghost, p):
             continue
         # rows whose source lies below the bottom wall (e_lz > 0) ...
         for z in range(0, min(ez, lz)):
-            out[l, :, z] = ghost[0, ez - z - 1, l]
+            out[l, :, z] = ghost_value(0, ez - z - 1, l, ex)
         # ... or above the top wall (e_lz < 0)
         for z in range(max(lz + ez, 0), lz):
-            out[l, :, z] = ghost[1, z - ez - lz, l]
+            out[l, :, z] = ghost_value(1, z - ez - lz, l, ex)
     return out
 
 
