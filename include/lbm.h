@@ -39,7 +39,8 @@
  * the constant population set of the virtual row -1-i below the bottom wall,
  * ghost[1][i] that of row Lz+i above the top wall.  A pull whose source row
  * lies outside [0, Lz) reads this table (the paper's bc step on rows 0..2 and
- * Lz-3..Lz-1, Sec. III.B).
+ * Lz-3..Lz-1, Sec. III.B): as it stands (Dirichlet walls), or rescaled per
+ * ghost site so that the walls conserve mass (LBM_WALL_DIFFUSE, see lbm_step).
  *
  * Memory and streams.  Pointers marked (device) are device memory, (host)
  * host memory.  All buffers are owned by the caller; the library allocates,
@@ -62,7 +63,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1u
+#define LBM_ABI_VERSION 2u
 #define LBM_Q 37
 #define LBM_MAX_MODES 32 /* interface modes per front accepted by lbm_init_rt3 */
 
@@ -83,8 +84,10 @@ enum lbm_precision { LBM_F64 = 0, LBM_F32_DEV = 1 };
 enum lbm_flags {
     LBM_PERIODIC_Z = 1u, /* test mode: z wraps like x, no walls, ghost unused           */
     LBM_NO_COLLIDE = 2u, /* test mode: streaming and walls only                          */
-    LBM_ADJ_F32 = 4u     /* adjoint buffers (lam_seed, lam_in/lam_out, lam0) are float,
+    LBM_ADJ_F32 = 4u,    /* adjoint buffers (lam_seed, lam_in/lam_out, lam0) are float,
                             not double; the adjoint arithmetic stays double            */
+    LBM_WALL_DIFFUSE = 8u /* mass-conserving diffuse walls instead of Dirichlet walls
+                            (lbm_step); not with LBM_PERIODIC_Z                       */
 };
 
 typedef struct lbm_params {
@@ -145,10 +148,21 @@ int lbm_init_rt3(const lbm_params *params, const lbm_rt3_desc *desc, const doubl
  * Sec. III.A eq. LBE with the force-shifted equilibrium (velocity u + g tau,
  * temperature T + tau (1 - tau) g^2 / d) and the moment definitions; the
  * propagate/bc/collide order of Sec. III.B.  For every site (x, z) and l:
- *     g_l(x, z) = f_in_l((x - e_lx) mod Lx, z - e_lz)   (or the wall table)
+ *     g_l(x, z) = f_in_l((x - e_lx) mod Lx, z - e_lz)   (or a ghost site)
  *     rho, u, T = moments of g
  *     f_out_l   = g_l - (g_l - f^eq_l)/tau
  * with f^eq the 4th-order Hermite expansion of the Maxwellian.
+ *
+ * Walls (the bc step of Sec. III.B, which only says that rows 0..2 and
+ * Lz-3..Lz-1 are adjusted at rigid walls; both rules are readings of it).
+ * Sources with z - e_lz outside [0, Lz) are ghost sites, row i of a side
+ * being row -1-i (bottom) or Lz+i (top):
+ *   Dirichlet (default): the ghost site holds its table row ghost[side][i][.].
+ *   LBM_WALL_DIFFUSE: ghost site s = (x_g, k) holds ghost[side][i][l] M(s)/S,
+ *     M(s) = sum over m of f_in_m(x_g - e_mx, k - e_mz) for the m whose source
+ *     row lies inside [0, Lz) (the mass streaming into s), S = sum of the table
+ *     row over the l with k + e_lz inside [0, Lz); the lattice's total mass is
+ *     then conserved by every step.
  *
  *   ghost        (device) wall table [2][3][37]; may be NULL with LBM_PERIODIC_Z
  *   f_in         (device) state buffer, read
@@ -236,21 +250,27 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  * writes lam_out = dJ/df_in.  With m = (rho, u, T) the step's pre-collision
  * moments at site x, omega = 1/tau and mu = omega (dF/dm)^T lam_in(x),
  *     G_l(x) = (1 - omega) lam_in_l(x) + alpha + beta . xi_l + gamma |xi_l|^2,
- *     lam_out_l(y) = G_l(y + e_l)  (x periodic; 0 where y + e_l is beyond a wall),
+ *     lam_out_l(y) = G_l(y + e_l)  (x periodic) where y + e_l is inside the walls,
  *     alpha = mu_rho - mu_u . u/rho + mu_T (|u|^2 - 2T)/(2 rho),
  *     beta = mu_u/rho - mu_T u/rho,  gamma = mu_T/(2 rho).
- * The wall table is constant and receives no derivative.
+ * Where y + e_l is a ghost site s: 0 for the Dirichlet wall (the table is
+ * constant and receives no derivative); with LBM_WALL_DIFFUSE
+ *     lam_out_l(y) = sum_m c_m G_m(s + e_m) / sum_m c_m
+ * over the m with s + e_m inside the walls, c_m = the table row of s.
  *
+ *   ghost    (device) the wall table the forward step used; required with
+ *            LBM_WALL_DIFFUSE, otherwise unused and may be NULL
  *   moments  (device) double [4][Lx][Lz]: rho, u_x, u_z, T written by the
  *            forward lbm_step's moments_out (may be NULL with LBM_NO_COLLIDE)
  *   lam_in   (device) [37][Lx][Lz], double (float with LBM_ADJ_F32)
- *   lam_out  (device) same type and shape, must not overlap lam_in or moments
- * The adjoint arithmetic is double; params->precision only names the
- * forward state it belongs to.
+ *   lam_out  (device) same type and shape, must not overlap lam_in, moments
+ *            or ghost
+ * The adjoint arithmetic is double; params->precision names the forward
+ * state it belongs to and the element type of ghost.
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
  */
-int lbm_adjoint_step(const lbm_params *params, const double *moments, const void *lam_in,
-                     void *lam_out, lbm_stream_t stream);
+int lbm_adjoint_step(const lbm_params *params, const void *ghost, const double *moments,
+                     const void *lam_in, void *lam_out, lbm_stream_t stream);
 
 /*
  * lbm_init_rt3_vjp -- gradient of lbm_init_rt3 with respect to the mode

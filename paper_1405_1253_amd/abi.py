@@ -14,11 +14,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 Q = 37
 MAX_MODES = 32
 F64, F32_DEV = 0, 1
-PERIODIC_Z, NO_COLLIDE, ADJ_F32 = 1, 2, 4
+PERIODIC_Z, NO_COLLIDE, ADJ_F32, WALL_DIFFUSE = 1, 2, 4, 8
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EALIAS", -3: "LBM_EALIGN",
           -4: "LBM_EHIP", -5: "LBM_ESCRATCH", -6: "LBM_EVERSION"}
@@ -76,7 +76,7 @@ def load():
         lib.lbm_last_hip_error.restype = ctypes.c_char_p
         lib.lbm_objective.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, ctypes.c_double,
                                       ctypes.c_double, _VP, _VP, _VP, ctypes.c_size_t, _VP]
-        lib.lbm_adjoint_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP]
+        lib.lbm_adjoint_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
         lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP]
         lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
@@ -85,6 +85,13 @@ def load():
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
     return _LIB
+
+
+def wall_flag(wall):
+    """Flag bits of a wall rule name: "dirichlet" (the default) or "diffuse"."""
+    if wall not in ("dirichlet", "diffuse"):
+        raise ValueError(f"unknown wall rule {wall!r}")
+    return WALL_DIFFUSE if wall == "diffuse" else 0
 
 
 def make_params(lx, lz, tau, g, precision=F64, flags=0):
@@ -185,10 +192,11 @@ def lbm_objective(params, desc, f, wk, wl, j_out, lam_seed=None, scratch=None, s
     _check(st, "lbm_objective")
 
 
-def lbm_adjoint_step(params, moments, lam_in, lam_out, stream=None):
-    """lam_out = (d step / d f_in)^T lam_in (see include/lbm.h)."""
-    st = load().lbm_adjoint_step(ctypes.byref(params), _ptr(moments), _ptr(lam_in), _ptr(lam_out),
-                                 _stream(stream))
+def lbm_adjoint_step(params, ghost, moments, lam_in, lam_out, stream=None):
+    """lam_out = (d step / d f_in)^T lam_in (see include/lbm.h).  ``ghost`` is
+    the forward step's wall table (needed with WALL_DIFFUSE, else may be None)."""
+    st = load().lbm_adjoint_step(ctypes.byref(params), _ptr(ghost), _ptr(moments), _ptr(lam_in),
+                                 _ptr(lam_out), _stream(stream))
     _check(st, "lbm_adjoint_step")
 
 

@@ -14,8 +14,17 @@
 // own 37 lam values and 4 moments and writes G_l to site x - e_l: every
 // output element has exactly one writer (a permutation), so the kernel moves
 // 37 + 4 reads and 37 writes per site.  Rows y whose source y + e_l lies
-// beyond a wall receive an explicit zero (those pulls read the constant wall
-// table, which carries no derivative).
+// beyond a wall receive an explicit zero with the Dirichlet wall (those pulls
+// read the constant wall table, which carries no derivative).
+//
+// Diffuse wall.  The forward ghost site s = y + e_l emits c_m M(s) with
+// M(s) = sum of the populations streaming into it, so every such population
+// receives A(s) = sum_m c_m G_m(s + e_m) over the m pointing back into the
+// lattice (c_m = table row / its sum over those m).  The step kernel parks
+// G_{-l}(y) in the slot (l, y) that A(y + e_l) will fill (the slots of one
+// ghost site are exactly the slots its sum reads, by the e -> -e pairing),
+// and a second kernel with one thread per ghost site reads its slots, forms
+// A and writes it back into the same slots: no other thread touches them.
 //
 // Equilibrium derivatives.  With P(x) = A0 + A1 x + A2 x^2 + x^3/6 + x^4/24
 // (common.h), x = xi . v, u2 = |v|^2, th = T_eq - 1:
@@ -170,9 +179,18 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
         } else {
             if (zd >= 0 && zd < a.lz) dst[zd] = G;
             // lam_out_l(z) = G_l(z + e_lz) has no writer when row z + e_lz lies
-            // beyond a wall: that pull read the constant wall table
+            // beyond a wall: zero for the Dirichlet wall (that pull read the
+            // constant table); the diffuse wall parks G_{-l} of this site there
             const int zsrc = z + EZ[l];
-            if (zsrc < 0 || zsrc >= a.lz) lam_out[(size_t)l * N + site] = L(0);
+            if (zsrc < 0 || zsrc >= a.lz) {
+                L park = L(0);
+                if (a.flags & F_WALL_DIFFUSE) {
+                    const int o = l == 0 ? 0 : ((l & 1) ? l + 1 : l - 1);   // -e_l
+                    park = (L)(keep * lam[o] + alpha + (EX[o] * bx + EZ[o] * bz) +
+                               gamma * XI2_SHELL[SHELL[o]]);
+                }
+                lam_out[(size_t)l * N + site] = park;
+            }
         }
     }
 }
@@ -187,13 +205,60 @@ __global__ __launch_bounds__(BLOCK) void adjoint_step_kernel(AdjointArgs a, int 
         adjoint_tile<false, L>(a, x, z0);
 }
 
+// Diffuse wall, second pass: one thread per ghost site (x_g, row k), reading
+// the parked G values of the sites it emits to and writing A into the slots
+// of the populations that stream into it (the same slots).
+template <typename L, typename GT>
+__global__ __launch_bounds__(BLOCK) void adjoint_wall_kernel(AdjointArgs a) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= 6 * a.lx) return;
+    L *__restrict__ lam = static_cast<L *>(a.lam_out);
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    const int xg = t % a.lx, row = t / a.lx;      // row = side * 3 + i
+    const int k = row < 3 ? -1 - row : a.lz + (row - 3);
+    const GT *gh = static_cast<const GT *>(a.ghost) + (size_t)row * Q;
+    constexpr bool dev = std::is_same<GT, float>::value;   // FP32 table stores f - w
+    double S = 0.0, A = 0.0;
+#pragma unroll
+    for (int m = 1; m < Q; ++m) {
+        const int zd = k + EZ[m];   // the ghost site emits population m to (xg + e_mx, zd)
+        if (zd < 0 || zd >= a.lz) continue;
+        const double c = (double)gh[m] + (dev ? W[m] : 0.0);
+        const int o = (m & 1) ? m + 1 : m - 1;
+        const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
+        S += c;
+        A += c * (double)lam[(size_t)o * N + (size_t)xd * (size_t)a.lz + (size_t)zd];
+    }
+    const L out = (L)(A / S);
+#pragma unroll
+    for (int m = 1; m < Q; ++m) {
+        const int zs = k - EZ[m];   // population m streams into the ghost site from (xg - e_mx, zs)
+        if (zs < 0 || zs >= a.lz) continue;
+        const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
+        lam[(size_t)m * N + (size_t)xs * (size_t)a.lz + (size_t)zs] = out;
+    }
+}
+
 hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
     const int nzb = (a.lz + BLOCK - 1) / BLOCK;
     const dim3 grid((uint32_t)nzb * (uint32_t)a.lx);
-    if (a.flags & F_ADJ_F32)
+    const bool f32 = (a.flags & F_ADJ_F32) != 0;
+    if (f32)
         hipLaunchKernelGGL(adjoint_step_kernel<float>, grid, dim3(BLOCK), 0, s, a, nzb);
     else
         hipLaunchKernelGGL(adjoint_step_kernel<double>, grid, dim3(BLOCK), 0, s, a, nzb);
+    if (a.flags & F_WALL_DIFFUSE) {
+        const dim3 wgrid((uint32_t)((6 * a.lx + BLOCK - 1) / BLOCK));
+        const bool gf = a.precision == P_F32_DEV;
+        if (f32 && gf)
+            hipLaunchKernelGGL((adjoint_wall_kernel<float, float>), wgrid, dim3(BLOCK), 0, s, a);
+        else if (f32)
+            hipLaunchKernelGGL((adjoint_wall_kernel<float, double>), wgrid, dim3(BLOCK), 0, s, a);
+        else if (gf)
+            hipLaunchKernelGGL((adjoint_wall_kernel<double, float>), wgrid, dim3(BLOCK), 0, s, a);
+        else
+            hipLaunchKernelGGL((adjoint_wall_kernel<double, double>), wgrid, dim3(BLOCK), 0, s, a);
+    }
     return hipGetLastError();
 }
 

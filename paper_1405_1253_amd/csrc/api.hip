@@ -32,7 +32,9 @@ int check_params(const lbm_params *p, bool *empty) {
     if (p->lx < 0 || p->lz < 0) return LBM_EINVAL;
     if ((long long)p->lx * (long long)p->lz > MAX_SITES) return LBM_EINVAL;
     if (p->precision != LBM_F64 && p->precision != LBM_F32_DEV) return LBM_EINVAL;
-    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32)) return LBM_EINVAL;
+    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32 | LBM_WALL_DIFFUSE))
+        return LBM_EINVAL;
+    if ((p->flags & LBM_PERIODIC_Z) && (p->flags & LBM_WALL_DIFFUSE)) return LBM_EINVAL;
     if (p->reserved != 0) return LBM_EINVAL;
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return LBM_EINVAL;
     if (!(p->g >= 0.0) || !isfinite(p->g)) return LBM_EINVAL;
@@ -307,20 +309,26 @@ int lbm_objective(const lbm_params *p, const lbm_rt3_desc *d, const void *f, dou
     return hip_status(lbm::launch_objective(a, p->precision, (hipStream_t)stream));
 }
 
-int lbm_adjoint_step(const lbm_params *p, const double *moments, const void *lam_in, void *lam_out,
-                     lbm_stream_t stream) {
+int lbm_adjoint_step(const lbm_params *p, const void *ghost, const double *moments, const void *lam_in,
+                     void *lam_out, lbm_stream_t stream) {
     bool empty = false;
     int st = check_params(p, &empty);
     if (st != LBM_OK) return st;
     if (!lam_in || !lam_out || (!moments && !(p->flags & LBM_NO_COLLIDE))) return LBM_EINVAL;
-    if (!aligned(lam_in, 16) || !aligned(lam_out, 16) || !aligned(moments, 16)) return LBM_EALIGN;
+    if (!ghost && (p->flags & LBM_WALL_DIFFUSE)) return LBM_EINVAL;
+    if (!aligned(lam_in, 16) || !aligned(lam_out, 16) || !aligned(moments, 16) || !aligned(ghost, 8))
+        return LBM_EALIGN;
     if (empty) return LBM_OK;
     const size_t lb = lam_bytes(p), mb = field_bytes(p);
-    if (overlap(lam_in, lb, lam_out, lb) || overlap(moments, mb, lam_out, lb)) return LBM_EALIAS;
+    if (overlap(lam_in, lb, lam_out, lb) || overlap(moments, mb, lam_out, lb) ||
+        overlap(ghost, ghost_bytes(p), lam_out, lb))
+        return LBM_EALIAS;
     lbm::AdjointArgs a;
     a.mom = moments;
     a.lam_in = lam_in;
     a.lam_out = lam_out;
+    a.ghost = ghost;
+    a.precision = p->precision;
     a.lx = p->lx;
     a.lz = p->lz;
     a.tau = p->tau;

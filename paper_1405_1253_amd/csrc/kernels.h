@@ -8,7 +8,7 @@
 
 namespace lbm {
 
-enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u };
+enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u, F_WALL_DIFFUSE = 8u };
 enum : int { P_F64 = 0, P_F32_DEV = 1 };
 
 struct StepArgs {
@@ -63,6 +63,8 @@ struct AdjointArgs {
     const double *mom;     // [4][lx][lz] pre-collision moments of the step
     const void *lam_in;    // [37][lx][lz] dJ/df*_t (double, or float with F_ADJ_F32)
     void *lam_out;         // [37][lx][lz] dJ/df*_{t-1}
+    const void *ghost;     // [2][3][37] wall table of the forward step (F_WALL_DIFFUSE)
+    int precision;         // element type of ghost (P_F64 / P_F32_DEV)
     int lx, lz;
     double tau, omega, g;
     uint32_t flags;

@@ -15,9 +15,16 @@
 // FP64 ridge.
 //
 // Walls.  Blocks within 3 rows of either wall (or of a ragged end) take a
-// second, block-uniform code path that substitutes the wall table for
-// sources outside [0, Lz) or wraps z in the periodic test mode; all other
-// blocks run the branch-free path.
+// second, block-uniform code path that substitutes ghost sites for sources
+// outside [0, Lz) or wraps z in the periodic test mode; all other blocks run
+// the branch-free path.  The Dirichlet wall reads its ghost populations from
+// the wall table.  The diffuse wall (F_WALL_DIFFUSE, mass-conserving
+// reading of the bc step of Sec. III.B) gives ghost site s the table row's
+// populations times M(s)/S: M(s) is the mass that streams from the lattice
+// into s in this pull, S the sum of the table row over the populations that
+// point back into the lattice, so s returns exactly what it received.  The
+// block first evaluates M/S for the 2 x 3 x 7 ghost sites its column can
+// pull from (columns x-3..x+3) into LDS.
 #include "common.h"
 #include "kernels.h"
 
@@ -34,16 +41,53 @@ struct Elt<P_F32_DEV> {
     using T = float;
 };
 
-template <int PREC, bool EDGE>
-__device__ __forceinline__ void step_tile(const StepArgs &a, int x, int z0) {
+// Full population value of a state or table element (FP32 stores f - w).
+template <int PREC, typename E>
+__device__ __forceinline__ double full_value(E v, int l) {
+    return PREC == P_F64 ? (double)v : (double)v + W[l];
+}
+
+// M/S of the diffuse wall for the ghost sites (side, row i, column x + dx),
+// dx = -3..3, one lane each (wave 0, lanes 0..41).
+template <int PREC, typename E>
+__device__ __forceinline__ void diffuse_wall_ratios(const StepArgs &a, const E *fin, const E *ghost, int x,
+                                                    double (*ratio)[3][7]) {
+    const int t = (int)threadIdx.x;
+    if (t >= 42) return;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    const int side = t / 21, i = (t % 21) / 7, dx = t % 7 - 3;
+    const int k = side == 0 ? -1 - i : a.lz + i;
+    const int xg = wrap(x + dx, a.lx);
+    const E *row = ghost + (size_t)(side * 3 + i) * Q;
+    double M = 0.0, S = 0.0;
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+        const int zs = k - EZ[m];   // population m streams from (xg - e_mx, zs) into the ghost site
+        if (zs >= 0 && zs < a.lz) {
+            const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
+            M += full_value<PREC>(fin[(size_t)m * N + (size_t)xs * (size_t)a.lz + (size_t)zs], m);
+        }
+        const int zd = k + EZ[m];   // population m leaves the ghost site towards row zd
+        if (zd >= 0 && zd < a.lz) S += full_value<PREC>(row[m], m);
+    }
+    ratio[side][i][dx + 3] = M / S;
+}
+
+// One site (x, z) of the step.  EDGE: rows within 3 of a wall may pull from
+// ghost sites; lanes with z >= Lz only read (a valid row) and store nothing,
+// nor do lanes with store == false.  DIFFUSE: ghost sites are the diffuse
+// wall's, with M/S from ratio (columns x-3..x+3).
+template <int PREC, bool EDGE, bool DIFFUSE>
+__device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool store,
+                                          const double (*ratio)[3][7]) {
     using E = typename Elt<PREC>::T;
     const size_t N = (size_t)a.lx * (size_t)a.lz;
     const E *__restrict__ fin = static_cast<const E *>(a.f_in);
     E *__restrict__ fout = static_cast<E *>(a.f_out);
     const E *__restrict__ ghost = static_cast<const E *>(a.ghost);
-    const int z = z0 + (int)threadIdx.x;
-    const bool active = !EDGE || z < a.lz;
+    const bool active = store && (!EDGE || z < a.lz);
     const int zq = (EDGE && z >= a.lz) ? a.lz - 1 : z;   // idle lanes read a valid row
+    constexpr bool diffuse = EDGE && DIFFUSE;
 
     // ---- propagate + bc: gather the 37 incoming populations -------------
     E v[Q];
@@ -55,14 +99,24 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, int x, int z0) {
             v[l] = src[z - EZ[l]];
         } else {
             const int zs = zq - EZ[l];
-            if (a.flags & F_PERIODIC_Z)
+            if (diffuse) {
+                if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
+                    const int side = zs < 0 ? 0 : 1, i = zs < 0 ? -zs - 1 : zs - a.lz;
+                    const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) *
+                                     ratio[side][i][3 - EX[l]];
+                    v[l] = (E)(PREC == P_F64 ? f : f - W[l]);
+                } else {
+                    v[l] = src[zs];
+                }
+            } else if (a.flags & F_PERIODIC_Z) {
                 v[l] = src[wrap(zs, a.lz)];
-            else if (zs < 0)
+            } else if (zs < 0) {
                 v[l] = ghost[(-zs - 1) * Q + l];
-            else if (zs >= a.lz)
+            } else if (zs >= a.lz) {
                 v[l] = ghost[(3 + zs - a.lz) * Q + l];
-            else
+            } else {
                 v[l] = src[zs];
+            }
         }
     }
 
@@ -182,8 +236,12 @@ struct StepShape<P_F32_DEV> {
     static constexpr int BS = 256, ZT = 2;
 };
 
+// Interior and Dirichlet-wall tiles.  With diffuse walls (skip_wall) the
+// rows 0..2 and Lz-3..Lz-1 are left to step_wall_kernel: this kernel then
+// carries none of the diffuse wall's code or registers.
 template <int PREC>
-__global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, int nzb, uint32_t nblocks) {
+__global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, int nzb, uint32_t nblocks,
+                                                                   int skip_wall) {
     constexpr int BS = StepShape<PREC>::BS, ZT = StepShape<PREC>::ZT;
     const uint32_t t = xcd_tile(blockIdx.x, nblocks);
     const int x = (int)(t / (uint32_t)nzb);
@@ -191,12 +249,28 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, i
     for (int k = 0; k < ZT; ++k) {
         const int z0 = (zt + k) * BS;
         if (z0 >= a.lz) break;
+        const int z = z0 + (int)threadIdx.x;
         const bool edge = (z0 < 3) || (z0 + BS + 3 > a.lz);
         if (edge)
-            step_tile<PREC, true>(a, x, z0);
+            step_site<PREC, true, false>(a, x, z, !skip_wall || (z >= 3 && z < a.lz - 3), nullptr);
         else
-            step_tile<PREC, false>(a, x, z0);
+            step_site<PREC, false, false>(a, x, z, true, nullptr);
     }
+}
+
+// Diffuse-wall rows: one wavefront per column.  Lanes 0..41 evaluate M/S of
+// the 2 x 3 x 7 ghost sites the column pulls from, then lane j < min(Lz, 6)
+// steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row when Lz < 6).
+template <int PREC>
+__global__ __launch_bounds__(64) void step_wall_kernel(StepArgs a) {
+    using E = typename Elt<PREC>::T;
+    __shared__ double ratio[2][3][7];
+    const int x = (int)blockIdx.x;
+    diffuse_wall_ratios<PREC>(a, static_cast<const E *>(a.f_in), static_cast<const E *>(a.ghost), x,
+                              ratio);
+    __syncthreads();
+    const int j = (int)threadIdx.x, nw = a.lz < 6 ? a.lz : 6;
+    if (j < nw) step_site<PREC, true, true>(a, x, j < 3 ? j : a.lz - (nw - j), true, ratio);
 }
 
 template <int PREC>
@@ -204,7 +278,9 @@ static void launch_prec(const StepArgs &a, hipStream_t s) {
     constexpr int BS = StepShape<PREC>::BS, span = BS * StepShape<PREC>::ZT;
     const int nzb = (a.lz + span - 1) / span;
     const uint32_t nblocks = (uint32_t)nzb * (uint32_t)a.lx;
-    hipLaunchKernelGGL(step_kernel<PREC>, dim3(nblocks), dim3(BS), 0, s, a, nzb, nblocks);
+    const int diffuse = (a.flags & F_WALL_DIFFUSE) ? 1 : 0;
+    hipLaunchKernelGGL(step_kernel<PREC>, dim3(nblocks), dim3(BS), 0, s, a, nzb, nblocks, diffuse);
+    if (diffuse) hipLaunchKernelGGL(step_wall_kernel<PREC>, dim3((uint32_t)a.lx), dim3(64), 0, s, a);
 }
 
 hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s) {

@@ -43,12 +43,14 @@ class RolloutConfig:
     wl: float = 1.0
     moment_budget_bytes: int = 64 << 30
     adj_precision: str = "f64"     # "f32": adjoint buffers in float (LBM_ADJ_F32)
+    wall: str = "dirichlet"        # or "diffuse" (LBM_WALL_DIFFUSE)
 
     @classmethod
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
         kw.setdefault("ckpt_every", wl.ckpt_every or 100)
         kw.setdefault("precision", wl.precision)
         kw.setdefault("adj_precision", wl.adj_precision)
+        kw.setdefault("wall", wl.wall)
         return cls(wl.lx, wl.lz, wl.tau, wl.g, wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k,
                    modes.phase, wl.steps if nsteps is None else nsteps, **kw)
 
@@ -61,7 +63,8 @@ class Rollout:
         self.device = torch.device(device)
         self.params = abi.make_params(c.lx, c.lz, c.tau, c.g,
                                       abi.F64 if c.precision == "f64" else abi.F32_DEV,
-                                      abi.ADJ_F32 if c.adj_precision == "f32" else 0)
+                                      (abi.ADJ_F32 if c.adj_precision == "f32" else 0)
+                                      | abi.wall_flag(c.wall))
         self.ldtype = torch.float32 if c.adj_precision == "f32" else torch.float64
         self.desc = abi.RT3Desc(c.t_d, c.t_m, c.t_u, c.width, c.k, c.phase)
         self.sdtype = torch.float64 if c.precision == "f64" else torch.float32
@@ -113,7 +116,7 @@ class Rollout:
         t = c.nsteps
         while t >= 1:
             if t >= self.first_kept:
-                abi.lbm_adjoint_step(self.params, self.kept[t - self.first_kept], self.lam[li],
+                abi.lbm_adjoint_step(self.params, self.ghost, self.kept[t - self.first_kept], self.lam[li],
                                      self.lam[1 - li])
                 li = 1 - li
                 t -= 1
@@ -128,7 +131,7 @@ class Rollout:
                 cur = 1 - cur
             self.recomputed_steps += b - a
             for s in range(b, a, -1):
-                abi.lbm_adjoint_step(self.params, self.segbuf[s - a - 1], self.lam[li],
+                abi.lbm_adjoint_step(self.params, self.ghost, self.segbuf[s - a - 1], self.lam[li],
                                      self.lam[1 - li])
                 li = 1 - li
             t = a

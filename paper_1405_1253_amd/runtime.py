@@ -32,6 +32,7 @@ class Lattice:
     # ---- construction -----------------------------------------------------
     @classmethod
     def from_workload(cls, wl: Workload, modes=None, amp=None, device="cuda", **kw):
+        kw["flags"] = kw.get("flags", 0) | abi.wall_flag(wl.wall)
         lat = cls(wl.lx, wl.lz, wl.tau, wl.g, precision=wl.precision, device=device, **kw)
         modes = modes if modes is not None else draw_modes(wl.seed)
         a = modes.amp if amp is None else amp

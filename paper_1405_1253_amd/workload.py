@@ -48,6 +48,7 @@ class Workload:
     g_override: float = None  # gravity when not scaled with Lz
     t_m_diag: float = None    # middle temperature of the tent-map diagnostics
                               # (the single-front run's "virtual" T_m)
+    wall: str = "dirichlet"   # wall rule: "dirichlet" or "diffuse" (mass-conserving)
 
     @property
     def g(self) -> float:
@@ -68,6 +69,10 @@ WORKLOADS = {
         Workload("rt3_4096x12288", 4096, 12288, 1000, "f64", 1405),
         Workload("rt3_4096x12288_f32", 4096, 12288, 20000, "f32dev", 1405),
         Workload("rt3_512x1536_adj", 512, 1536, 2000, "f64", 1253, ckpt_every=100),
+        Workload("rt3_4096x12288_diffuse", 4096, 12288, 1000, "f64", 1405, wall="diffuse"),
+        Workload("rt3_4096x12288_f32_diffuse", 4096, 12288, 20000, "f32dev", 1405, wall="diffuse"),
+        Workload("rt3_512x1536_adj_diffuse", 512, 1536, 2000, "f64", 1253, ckpt_every=100,
+                 wall="diffuse"),
         Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250,
                  adj_precision="f32"),
         # The runs of Sec. IV, Table II: 2400 x 6144, g = 1.5e-5, T 1.025/1/0.975,

@@ -65,7 +65,9 @@ def test_step_rejects_bad_arguments(abi):
     assert _call_step(abi, mk(-1, 16, 0.7, 0.0)) == -1
     assert _call_step(abi, mk(1 << 15, 1 << 15, 0.7, 0.0)) == -1  # too many sites
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, precision=7)) == -1
-    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=8)) == -1
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=16)) == -1          # unknown flag
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=abi.PERIODIC_Z | abi.WALL_DIFFUSE)) == -1
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=abi.WALL_DIFFUSE), ghost=None) == -1
     p = mk(16, 16, 0.7, 0.0)
     p.abi_version = 99
     assert _call_step(abi, p) == -6
@@ -112,8 +114,12 @@ def test_moments_and_init_reject_bad_arguments(abi):
                              3 << 30, need, None) == -1
     assert lib.lbm_objective(ctypes.byref(p), ctypes.byref(desc), 1 << 30, 1.0, 1.0, 1 << 20, None,
                              3 << 30, 64, None) == -5
-    assert lib.lbm_adjoint_step(ctypes.byref(p), None, 1 << 30, 3 << 30, None) == -1
-    assert lib.lbm_adjoint_step(ctypes.byref(p), 1 << 20, 1 << 30, (1 << 30) + 4096, None) == -2
+    assert lib.lbm_adjoint_step(ctypes.byref(p), None, None, 1 << 30, 3 << 30, None) == -1
+    assert lib.lbm_adjoint_step(ctypes.byref(p), None, 1 << 20, 1 << 30, (1 << 30) + 4096, None) == -2
+    # the diffuse wall's adjoint needs the wall table, which must not overlap lam_out
+    pd = abi.make_params(64, 64, 0.7, 1e-4, flags=abi.WALL_DIFFUSE)
+    assert lib.lbm_adjoint_step(ctypes.byref(pd), None, 1 << 20, 1 << 30, 3 << 30, None) == -1
+    assert lib.lbm_adjoint_step(ctypes.byref(pd), (3 << 30) + 64, 1 << 20, 1 << 30, 3 << 30, None) == -2
     assert lib.lbm_init_rt3_vjp(ctypes.byref(p), ctypes.byref(desc), 1 << 20, 1 << 30, 1 << 19,
                                 3 << 30, 8, None) == -5
 

@@ -42,21 +42,22 @@ def _state(lx, lz, tau, g, seed, steps=3, periodic=False):
 
 
 @pytest.mark.parametrize("lx,lz", [(128, 384), (37, 300), (5, 7), (2, 3)])
-@pytest.mark.parametrize("mode", ["walls", "periodic", "nocollide"])
+@pytest.mark.parametrize("mode", ["walls", "periodic", "nocollide", "diffuse", "diffuse_nocollide"])
 def test_adjoint_step_parity(abi, lx, lz, mode):
     p, f, ghost = _state(lx, lz, 0.7, 2e-3, lx + lz, periodic=(mode == "periodic"))
-    if mode == "nocollide":
-        p.no_collide = True
+    p.no_collide = mode.endswith("nocollide")
+    p.wall = "diffuse" if mode.startswith("diffuse") else "dirichlet"
     lam = np.random.default_rng(lx * lz).standard_normal((37, lx, lz))
     want = A.step_vjp(lam, f, ghost, p)
-    flags = (abi.PERIODIC_Z if p.periodic_z else 0) | (abi.NO_COLLIDE if p.no_collide else 0)
+    flags = ((abi.PERIODIC_Z if p.periodic_z else 0) | (abi.NO_COLLIDE if p.no_collide else 0)
+             | abi.wall_flag(p.wall))
     params = abi.make_params(lx, lz, p.tau, p.g, flags=flags)
     fin, gh = _t(f), _t(ghost)
     fout = torch.empty_like(fin)
     mom = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
     abi.lbm_step(params, gh, fin, fout, mom)
     lam_out = torch.full_like(fin, float("nan"))
-    abi.lbm_adjoint_step(params, mom, _t(lam), lam_out)
+    abi.lbm_adjoint_step(params, gh, mom, _t(lam), lam_out)
     got = lam_out.cpu().numpy()
     assert np.isfinite(got).all()
     assert _rel_max(got, want) <= 1e-12
@@ -99,36 +100,38 @@ def _rollout(wl, modes, nsteps, **kw):
     return Rollout(RolloutConfig.from_workload(wl, modes, nsteps=nsteps, **kw))
 
 
-def test_rollout_gradient_vs_oracle_128x384(abi):
+@pytest.mark.parametrize("wall", ["dirichlet", "diffuse"])
+def test_rollout_gradient_vs_oracle_128x384(abi, wall):
     from paper_1405_1253_amd.rollout import RTRollout
     wl = W.WORKLOADS["rt3_128x384"]
     m = W.draw_modes(wl.seed)
     n = 20
-    J_o, g_o = A.rollout_gradient(O.Params(wl.lx, wl.lz, wl.tau, wl.g),
+    J_o, g_o = A.rollout_gradient(O.Params(wl.lx, wl.lz, wl.tau, wl.g, wall=wall),
                                   O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase), m.amp, n)
     amp = torch.tensor(m.amp, device=DEV, requires_grad=True)
-    J = RTRollout.apply(amp, _rollout(wl, m, n))
+    J = RTRollout.apply(amp, _rollout(wl, m, n, wall=wall))
     J.backward()
     got = amp.grad.cpu().numpy()
     print(f"J gpu {J.item():.15e} oracle {J_o:.15e}; grad rel err {_rel_max(got, g_o):.2e}")
     assert abs(J.item() / J_o - 1) <= 1e-12
     assert _rel_max(got, g_o) <= 1e-10
     # recomputing from checkpoints gives the bitwise same gradient
-    r2 = _rollout(wl, m, n, ckpt_every=7, moment_budget_bytes=3 * 4 * wl.lx * wl.lz * 8)
+    r2 = _rollout(wl, m, n, ckpt_every=7, moment_budget_bytes=3 * 4 * wl.lx * wl.lz * 8, wall=wall)
     r2.forward(torch.as_tensor(m.amp, device=DEV))
     g2 = r2.backward().cpu().numpy()
     assert r2.recomputed_steps == n - 3
     assert np.array_equal(g2, got)
 
 
-def test_gradient_vs_finite_differences_512x1536(abi):
+@pytest.mark.parametrize("name", ["rt3_512x1536_adj", "rt3_512x1536_adj_diffuse"])
+def test_gradient_vs_finite_differences_512x1536(abi, name):
     """Central differences of the GPU forward at h = 1e-6 carry a rounding
     noise of about |dJ_noise| / (2h) with |dJ_noise| ~ 1e-12 (J ~ 30 after
     2000 steps of sums over 786k sites): the bar at h = 1e-6 is an absolute
     1e-6.  Larger h lowers that noise until the h^2 truncation takes over;
     at h = 1e-4 the adjoint must agree to 1e-6 relative to the largest
     gradient, showing that the remaining difference is the FD's own."""
-    wl = W.WORKLOADS["rt3_512x1536_adj"]
+    wl = W.WORKLOADS[name]
     m = W.draw_modes(wl.seed)
     r = _rollout(wl, m, wl.steps)
     amp0 = torch.as_tensor(m.amp, device=DEV)
@@ -159,22 +162,28 @@ def test_gradient_vs_finite_differences_512x1536(abi):
     assert errs[1e-4].max() <= 1e-6 * gmax
 
 
-def test_adjoint_step_float_buffers(abi):
+@pytest.mark.parametrize("wall", ["dirichlet", "diffuse"])
+def test_adjoint_step_float_buffers(abi, wall):
     """LBM_ADJ_F32: float adjoint buffers, double arithmetic.  Against the
     oracle fed the same float-rounded input, the only extra error is the
     final rounding to float: <= 2^-24 relative to each entry, bounded here
-    by 2^-23 of the largest entry."""
+    by 2^-23 of the largest entry.  The diffuse wall's parked values are
+    rounded to float once more before the wall pass sums them: at most
+    another 2^-24 of the largest entry."""
     lx, lz = 128, 384
     p, f, ghost = _state(lx, lz, 0.7, 2e-3, 9)
+    p.wall = wall
     lam = np.random.default_rng(8).standard_normal((37, lx, lz)).astype(np.float32)
     want = A.step_vjp(lam.astype(np.float64), f, ghost, p)
-    params = abi.make_params(lx, lz, p.tau, p.g, flags=abi.ADJ_F32)
+    params = abi.make_params(lx, lz, p.tau, p.g, flags=abi.ADJ_F32 | abi.wall_flag(wall))
     fout = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
     mom = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
-    abi.lbm_step(params, _t(ghost), _t(f), fout, mom)
+    gh = _t(ghost)
+    abi.lbm_step(params, gh, _t(f), fout, mom)
     out = torch.empty((37, lx, lz), dtype=torch.float32, device=DEV)
-    abi.lbm_adjoint_step(params, mom, _t(lam), out)
-    assert _rel_max(out.cpu().numpy().astype(np.float64), want) <= 2.0 ** -23
+    abi.lbm_adjoint_step(params, gh, mom, _t(lam), out)
+    assert _rel_max(out.cpu().numpy().astype(np.float64), want) <= (2.0 ** -23 if wall == "dirichlet"
+                                                                   else 3 * 2.0 ** -24)
 
 
 def test_gradient_float_storage_and_adjoint_vs_f64(abi):

@@ -1,0 +1,187 @@
+"""Diffuse (mass-conserving) wall, LBM_WALL_DIFFUSE, against the oracle.
+
+Bars: streaming with the diffuse wall within 4 ulp of the oracle in FP64
+(the wall rows are a product c_l M / S whose rounding order differs) and
+bit-exact away from the wall rows; within 2^-23 relative in FP32 deviation
+storage; the fused FP64 step within 1e-12 relative after 1 and 100 steps
+(128 x 384, ragged 37 x 300 and tiny lattices); the FP32 step within the
+FP32 deviation bound of 3e-7 per step; the lattice's total mass constant to
+rounding over 1000 steps; the full 4096 x 12288 lattice on sampled columns.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbm as O
+from paper_1405_1253_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1405_1253_amd import abi as mod
+    mod.load()
+    return mod
+
+
+def _rel(got, want):
+    return float(np.max(np.abs(got - want) / np.abs(want)))
+
+
+def _setup(lx, lz, tau, g, seed, nmodes=16, width=4.0):
+    m = W.draw_modes(seed, nmodes)
+    p = O.Params(lx, lz, tau, g, wall="diffuse")
+    desc = O.RT3(1.05, 1.0, 0.95, width, m.k, m.phase)
+    return m, p, desc
+
+
+def _gpu_init(abi, params, m, width=4.0):
+    f = torch.empty((37, params.lx, params.lz), dtype=torch.float64, device=DEV)
+    gh = torch.empty((2, 3, 37), dtype=torch.float64, device=DEV)
+    desc = abi.RT3Desc(1.05, 1.0, 0.95, width, m.k, m.phase)
+    abi.lbm_init_rt3(params, desc, torch.as_tensor(m.amp, device=DEV), f, gh)
+    return f, gh
+
+
+@pytest.mark.parametrize("lx,lz", [(64, 200), (37, 300), (5, 7), (2, 3)])
+def test_diffuse_streaming_f64(abi, lx, lz):
+    f = W.random_populations(300 + lx, lx, lz)
+    ghost = W.random_ghost(400 + lz)
+    params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F64, abi.NO_COLLIDE | abi.WALL_DIFFUSE)
+    fin = torch.as_tensor(f, device=DEV)
+    fout = torch.full_like(fin, float("nan"))
+    abi.lbm_step(params, torch.as_tensor(ghost, device=DEV), fin, fout)
+    got = fout.cpu().numpy()
+    want = O.pull(f, ghost, O.Params(lx, lz, 0.7, 1e-4, no_collide=True, wall="diffuse"))
+    assert np.abs(got - want).max() <= 4 * EPS * np.abs(want).max()
+    inner = slice(3, max(lz - 3, 3))
+    assert np.array_equal(got[:, :, inner], want[:, :, inner])
+    # each ghost site returns what it received: streaming conserves mass
+    assert abs(got.sum() / f.sum() - 1) <= 1e-14
+
+
+def test_diffuse_streaming_f32(abi):
+    lx, lz = 64, 200
+    w = abi.lbm_lattice()[1]
+    d = (W.random_populations(31, lx, lz) - w[:, None, None]).astype(np.float32)
+    dg = (W.random_ghost(32) - w[None, None, :]).astype(np.float32)
+    params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F32_DEV, abi.NO_COLLIDE | abi.WALL_DIFFUSE)
+    fout = torch.full((37, lx, lz), float("nan"), dtype=torch.float32, device=DEV)
+    abi.lbm_step(params, torch.as_tensor(dg, device=DEV), torch.as_tensor(d, device=DEV), fout)
+    got = fout.cpu().numpy().astype(np.float64) + w[:, None, None]
+    f = d.astype(np.float64) + w[:, None, None]
+    want = O.pull(f, dg.astype(np.float64) + w[None, None, :],
+                  O.Params(lx, lz, 0.7, 1e-4, no_collide=True, wall="diffuse"))
+    assert np.max(np.abs(got - want) / np.abs(want)) <= 2.0 ** -23
+    assert np.array_equal(fout.cpu().numpy()[:, :, 3:-3],
+                          O.pull(d, dg, O.Params(lx, lz, 0.7, 1e-4, no_collide=True))[:, :, 3:-3])
+
+
+@pytest.fixture(scope="module")
+def c1_diffuse():
+    wl = W.WORKLOADS["rt3_128x384"]
+    m, p, desc = _setup(wl.lx, wl.lz, wl.tau, wl.g, wl.seed)
+    f0, ghost = O.init_rt3(p, desc, m.amp)
+    f1 = O.step(f0, ghost, p)
+    f100 = O.run(f1, ghost, p, 99)
+    return wl, m, p, f0, ghost, f1, f100
+
+
+def test_diffuse_step_parity_f64_1_and_100_steps(abi, c1_diffuse):
+    wl, m, p, f0, ghost, f1, f100 = c1_diffuse
+    params = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, flags=abi.WALL_DIFFUSE)
+    fa, gh = _gpu_init(abi, params, m)
+    fb = torch.empty_like(fa)
+    abi.lbm_step(params, gh, fa, fb)
+    e1 = _rel(fb.cpu().numpy(), f1)
+    for _ in range(99):
+        abi.lbm_step(params, gh, fb, fa)
+        fa, fb = fb, fa
+    e100 = _rel(fb.cpu().numpy(), f100)
+    print(f"diffuse wall, FP64 max rel err: 1 step {e1:.3e}, 100 steps {e100:.3e}")
+    assert e1 <= 1e-12 and e100 <= 1e-12
+
+
+def test_diffuse_step_parity_ragged_and_tiny(abi):
+    for lx, lz, steps, width in ((37, 300, 12, 4.0), (2, 3, 3, 1.0), (4, 6, 3, 1.0), (1, 1, 3, 1.0)):
+        m, p, desc = _setup(lx, lz, 0.6, 3e-4, 7, nmodes=2, width=width)
+        f0, ghost = O.init_rt3(p, desc, m.amp)
+        want = O.run(f0, ghost, p, steps)
+        params = abi.make_params(lx, lz, 0.6, 3e-4, flags=abi.WALL_DIFFUSE)
+        fa, gh = _gpu_init(abi, params, m, width=width)
+        fb = torch.empty_like(fa)
+        for _ in range(steps):
+            abi.lbm_step(params, gh, fa, fb)
+            fa, fb = fb, fa
+        assert _rel(fa.cpu().numpy(), want) <= 1e-12, (lx, lz)
+
+
+def test_diffuse_step_f32_error_bound(abi, c1_diffuse):
+    """Same FP32 deviation bound as the Dirichlet wall: 3e-7 per step."""
+    from paper_1405_1253_amd.runtime import Lattice
+    wl, m, p, f0, ghost, f1, f100 = c1_diffuse
+    lat = Lattice(wl.lx, wl.lz, wl.tau, wl.g, precision="f32dev", flags=abi.WALL_DIFFUSE)
+    lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase, m.amp)
+    lat.step(1)
+    e1 = _rel(lat.populations().cpu().numpy(), f1)
+    lat.step(99)
+    e100 = _rel(lat.populations().cpu().numpy(), f100)
+    print(f"diffuse wall, FP32-dev max rel err: 1 step {e1:.2e}, 100 steps {e100:.2e}")
+    assert e1 <= 5e-7 and e100 <= 100 * 3e-7
+
+
+@pytest.mark.parametrize("prec,bound", [("f64", 1e-13), ("f32dev", 1e-6)])
+def test_diffuse_wall_conserves_mass_1000_steps(abi, prec, bound):
+    """Total mass over 1000 steps of the 128 x 384 three-layer workload: the
+    diffuse wall keeps it to rounding (FP64: ~1e-16 per step; FP32 deviation
+    storage: the per-step rounding of the stored deviations); the Dirichlet
+    wall's drift is printed beside it."""
+    from paper_1405_1253_amd.runtime import Lattice
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    drift = {}
+    for name, flags in (("diffuse", abi.WALL_DIFFUSE), ("dirichlet", 0)):
+        lat = Lattice(wl.lx, wl.lz, wl.tau, wl.g, precision=prec, flags=flags)
+        lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase, m.amp)
+        m0 = lat.sums()[0].item()
+        lat.step(1000)
+        drift[name] = abs(lat.sums()[0].item() / m0 - 1)
+    print(f"{prec}: relative mass drift over 1000 steps: diffuse {drift['diffuse']:.2e}, "
+          f"dirichlet {drift['dirichlet']:.2e}")
+    assert drift["diffuse"] <= bound
+
+
+def _oracle_column(wl, m, x, nsteps):
+    # a site depends on columns within 3 per step in the bulk and within 6
+    # per step at the diffuse wall rows (ghost sites gather from 3 columns
+    # either side of themselves)
+    half = 6 * nsteps
+    cols = (np.arange(x - half, x + half + 1)) % wl.lx
+    desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
+    f, ghost = O.init_rt3(O.Params(wl.lx, wl.lz, wl.tau, wl.g), desc, m.amp, columns=cols)
+    p = O.Params(len(cols), wl.lz, wl.tau, wl.g, wall="diffuse")
+    return O.run(f, ghost, p, nsteps)[:, half, :]
+
+
+def test_diffuse_fullsize_sampled_columns(abi):
+    from paper_1405_1253_amd.runtime import Lattice
+    wl = W.WORKLOADS["rt3_4096x12288_diffuse"]
+    m = W.draw_modes(wl.seed)
+    lat = Lattice.from_workload(wl)
+    assert lat.params.flags & abi.WALL_DIFFUSE
+    samples = (0, 1, 2048, 4095)
+    got = {}
+    for n in (1, 2):
+        lat.step(1)
+        got[n] = {x: lat.state[:, x, :].cpu().numpy() for x in samples}
+    del lat
+    torch.cuda.empty_cache()
+    worst = 0.0
+    for n, cols in got.items():
+        for x, g in cols.items():
+            worst = max(worst, _rel(g, _oracle_column(wl, m, x, n)))
+    print(f"diffuse wall, 4096 x 12288: max rel err over sampled columns {worst:.2e}")
+    assert worst <= 1e-12
