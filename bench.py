@@ -208,20 +208,28 @@ def main():
                      "kernel": "lbm::step_kernel", "wall_s": round(wall, 3)},
     }
     if not args.no_secondary and wl.precision == "f64":
-        wl32 = WORKLOADS.get(wl.name + "_f32")
-        if wl32 is not None:
-            lat = Lattice.from_workload(wl32)
-            s32, _ = time_steps(lat, args.steps, args.warmup)
+        # the same lattice in FP32 deviation storage, and both precisions with
+        # the diffuse (mass-conserving) wall rule
+        sec = {}
+        for suffix, key in (("_f32", "f32dev"), ("_diffuse", "diffuse_f64"),
+                            ("_f32_diffuse", "diffuse_f32dev")):
+            w2 = WORKLOADS.get(wl.name + suffix)
+            if w2 is None:
+                continue
+            lat = Lattice.from_workload(w2)
+            s2, _ = time_steps(lat, args.steps, args.warmup)
             lat.sums()
             del lat
             torch.cuda.empty_cache()
-            a32 = bytes_per_site("f32dev") * sites / (s32 / args.steps) / 1e9
-            out["secondary"] = {"f32dev_mlups": round(sites * args.steps / s32 / 1e6, 1),
-                                "f32dev_ms_per_step": round(s32 / args.steps * 1e3, 4),
-                                "f32dev_hbm_gbs": round(a32, 1),
-                                "f32dev_frac": round(a32 / HBM_PEAK_GBS, 4)}
+            a2 = bytes_per_site(w2.precision) * sites / (s2 / args.steps) / 1e9
+            sec.update({f"{key}_mlups": round(sites * args.steps / s2 / 1e6, 1),
+                        f"{key}_ms_per_step": round(s2 / args.steps * 1e3, 4),
+                        f"{key}_hbm_gbs": round(a2, 1),
+                        f"{key}_frac": round(a2 / HBM_PEAK_GBS, 4)})
+        out["secondary"] = sec
     if not args.no_adjoint:
         out["adjoint"] = [adjoint_ratio("rt3_512x1536_adj"),
+                          adjoint_ratio("rt3_512x1536_adj_diffuse"),
                           adjoint_ratio("rt3_2048x6144_adj", 60 << 30, warm=False)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -48,14 +48,13 @@ __device__ __forceinline__ double full_value(E v, int l) {
 }
 
 // M/S of the diffuse wall for the ghost sites (side, row i, column x + dx),
-// dx = -3..3, one lane each (wave 0, lanes 0..41).
+// dx = -3..3, one lane each (lanes 0..41 of a wavefront).
 template <int PREC, typename E>
 __device__ __forceinline__ void diffuse_wall_ratios(const StepArgs &a, const E *fin, const E *ghost, int x,
-                                                    double (*ratio)[3][7]) {
-    const int t = (int)threadIdx.x;
-    if (t >= 42) return;
+                                                    int lane, double (*ratio)[3][7]) {
+    if (lane >= 42) return;
     const size_t N = (size_t)a.lx * (size_t)a.lz;
-    const int side = t / 21, i = (t % 21) / 7, dx = t % 7 - 3;
+    const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
     const int k = side == 0 ? -1 - i : a.lz + i;
     const int xg = wrap(x + dx, a.lx);
     const E *row = ghost + (size_t)(side * 3 + i) * Q;
@@ -236,16 +235,42 @@ struct StepShape<P_F32_DEV> {
     static constexpr int BS = 256, ZT = 2;
 };
 
-// Interior and Dirichlet-wall tiles.  With diffuse walls (skip_wall) the
-// rows 0..2 and Lz-3..Lz-1 are left to step_wall_kernel: this kernel then
-// carries none of the diffuse wall's code or registers.
+// Diffuse-wall rows of one column per wavefront.  Lanes 0..41 evaluate M/S
+// of the 2 x 3 x 7 ghost sites the column pulls from, then lane j < min(Lz, 6)
+// steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row when Lz < 6).
+template <int PREC, int BS>
+__device__ __forceinline__ void wall_block(const StepArgs &a, uint32_t b) {
+    using E = typename Elt<PREC>::T;
+    constexpr int NW = BS / 64;   // columns per block
+    __shared__ double ratio[NW][2][3][7];
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const int x = __builtin_amdgcn_readfirstlane((int)b * NW + w);
+    const bool live = x < a.lx;
+    if (live)
+        diffuse_wall_ratios<PREC>(a, static_cast<const E *>(a.f_in), static_cast<const E *>(a.ghost), x, lane,
+                                  ratio[w]);
+    __syncthreads();
+    const int nw = a.lz < 6 ? a.lz : 6;
+    if (live && lane < nw)
+        step_site<PREC, true, true>(a, x, lane < 3 ? lane : a.lz - (nw - lane), true, ratio[w]);
+}
+
+// One launch per step.  With diffuse walls the first nwall blocks step the
+// wall rows (wall_block, BS/64 columns each) and the tile blocks leave rows
+// 0..2 and Lz-3..Lz-1 alone; issuing the short, latency-bound wall blocks
+// first lets them run under the bulk of the step.
 template <int PREC>
 __global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, int nzb, uint32_t nblocks,
-                                                                   int skip_wall) {
+                                                                   uint32_t nwall) {
     constexpr int BS = StepShape<PREC>::BS, ZT = StepShape<PREC>::ZT;
-    const uint32_t t = xcd_tile(blockIdx.x, nblocks);
+    if (blockIdx.x < nwall) {
+        wall_block<PREC, BS>(a, blockIdx.x);
+        return;
+    }
+    const uint32_t t = xcd_tile(blockIdx.x - nwall, nblocks);
     const int x = (int)(t / (uint32_t)nzb);
     const int zt = (int)(t % (uint32_t)nzb) * ZT;
+    const bool skip_wall = nwall != 0;
     for (int k = 0; k < ZT; ++k) {
         const int z0 = (zt + k) * BS;
         if (z0 >= a.lz) break;
@@ -258,29 +283,13 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, i
     }
 }
 
-// Diffuse-wall rows: one wavefront per column.  Lanes 0..41 evaluate M/S of
-// the 2 x 3 x 7 ghost sites the column pulls from, then lane j < min(Lz, 6)
-// steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row when Lz < 6).
-template <int PREC>
-__global__ __launch_bounds__(64) void step_wall_kernel(StepArgs a) {
-    using E = typename Elt<PREC>::T;
-    __shared__ double ratio[2][3][7];
-    const int x = (int)blockIdx.x;
-    diffuse_wall_ratios<PREC>(a, static_cast<const E *>(a.f_in), static_cast<const E *>(a.ghost), x,
-                              ratio);
-    __syncthreads();
-    const int j = (int)threadIdx.x, nw = a.lz < 6 ? a.lz : 6;
-    if (j < nw) step_site<PREC, true, true>(a, x, j < 3 ? j : a.lz - (nw - j), true, ratio);
-}
-
 template <int PREC>
 static void launch_prec(const StepArgs &a, hipStream_t s) {
     constexpr int BS = StepShape<PREC>::BS, span = BS * StepShape<PREC>::ZT;
     const int nzb = (a.lz + span - 1) / span;
     const uint32_t nblocks = (uint32_t)nzb * (uint32_t)a.lx;
-    const int diffuse = (a.flags & F_WALL_DIFFUSE) ? 1 : 0;
-    hipLaunchKernelGGL(step_kernel<PREC>, dim3(nblocks), dim3(BS), 0, s, a, nzb, nblocks, diffuse);
-    if (diffuse) hipLaunchKernelGGL(step_wall_kernel<PREC>, dim3((uint32_t)a.lx), dim3(64), 0, s, a);
+    const uint32_t nwall = (a.flags & F_WALL_DIFFUSE) ? (uint32_t)((a.lx + BS / 64 - 1) / (BS / 64)) : 0u;
+    hipLaunchKernelGGL(step_kernel<PREC>, dim3(nwall + nblocks), dim3(BS), 0, s, a, nzb, nblocks, nwall);
 }
 
 hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s) {
