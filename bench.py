@@ -208,22 +208,25 @@ def main():
                      "kernel": "lbm::step_kernel", "wall_s": round(wall, 3)},
     }
     if not args.no_secondary and wl.precision == "f64":
-        # the same lattice in FP32 deviation storage, and both precisions with
-        # the diffuse (mass-conserving) wall rule
+        # the same lattice in FP32 deviation storage, both precisions with the
+        # diffuse (mass-conserving) wall rule, and both on a single buffer
+        # (in-place steps come in pairs: step counts rounded up to even)
         sec = {}
         for suffix, key in (("_f32", "f32dev"), ("_diffuse", "diffuse_f64"),
-                            ("_f32_diffuse", "diffuse_f32dev")):
+                            ("_f32_diffuse", "diffuse_f32dev"), ("_inplace", "inplace_f64"),
+                            ("_f32_inplace", "inplace_f32dev")):
             w2 = WORKLOADS.get(wl.name + suffix)
             if w2 is None:
                 continue
+            n2 = args.steps + (args.steps % 2 if w2.inplace else 0)
             lat = Lattice.from_workload(w2)
-            s2, _ = time_steps(lat, args.steps, args.warmup)
+            s2, _ = time_steps(lat, n2, args.warmup + (args.warmup % 2 if w2.inplace else 0))
             lat.sums()
             del lat
             torch.cuda.empty_cache()
-            a2 = bytes_per_site(w2.precision) * sites / (s2 / args.steps) / 1e9
-            sec.update({f"{key}_mlups": round(sites * args.steps / s2 / 1e6, 1),
-                        f"{key}_ms_per_step": round(s2 / args.steps * 1e3, 4),
+            a2 = bytes_per_site(w2.precision) * sites / (s2 / n2) / 1e9
+            sec.update({f"{key}_mlups": round(sites * n2 / s2 / 1e6, 1),
+                        f"{key}_ms_per_step": round(s2 / n2 * 1e3, 4),
                         f"{key}_hbm_gbs": round(a2, 1),
                         f"{key}_frac": round(a2 / HBM_PEAK_GBS, 4)})
         out["secondary"] = sec

@@ -175,9 +175,43 @@ int lbm_step(const lbm_params *params, const void *ghost, const void *f_in, void
              double *moments_out, lbm_stream_t stream);
 
 /*
+ * lbm_step_inplace -- the step of lbm_step on one population buffer.
+ *
+ * Same arithmetic, walls and results as lbm_step (Sec. III.A eq. LBE,
+ * Sec. III.B step order), but the state lives in a single buffer instead of
+ * the paper's prv/nxt pair (Sec. III.B), halving its memory.  Steps alternate
+ * between two kinds; each moves the same 37 + 37 elements per site:
+ *   LBM_INPLACE_FROM_STATE: f holds a post-collision state in the standard
+ *     layout (as lbm_init_rt3 or lbm_step write it).  Each site pulls its
+ *     populations, collides, and writes f*_l to slot -l of the site x + e_l
+ *     it streams to; afterwards f holds the streamed form.
+ *   LBM_INPLACE_FROM_STREAMED: f holds the streamed form; each site reads
+ *     its populations from its own slots, collides and writes f*_l to slot
+ *     l; afterwards f holds the post-collision state in the standard layout.
+ * Streamed form: f[-l][x] is the next step's pre-collision population f_l(x)
+ * for every (l, x) whose pull source x - e_l lies inside the walls; where it
+ * lies beyond a wall, f[-l][x] holds the post-collision population of
+ * direction -l that left x towards that wall (the walls supply f_l(x)).
+ * Two steps of the two kinds equal two lbm_step calls; lbm_moments and the
+ * other entry points need the standard layout (an even number of steps).
+ *
+ *   ghost        (device) wall table [2][3][37]; may be NULL with LBM_PERIODIC_Z
+ *   f            (device) state buffer, read and written
+ *   kind         LBM_INPLACE_FROM_STATE or LBM_INPLACE_FROM_STREAMED
+ *   moments_out  (device, nullable) as for lbm_step
+ *   scratch      (device) with LBM_WALL_DIFFUSE: at least lbm_scratch_bytes
+ *                bytes, overwritten (the ghost-site masses); otherwise unused
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION,
+ * LBM_EHIP.
+ */
+enum lbm_inplace_kind { LBM_INPLACE_FROM_STATE = 0, LBM_INPLACE_FROM_STREAMED = 1 };
+int lbm_step_inplace(const lbm_params *params, const void *ghost, void *f, int kind,
+                     double *moments_out, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+
+/*
  * lbm_scratch_bytes -- size of the scratch buffer that lbm_moments,
- * lbm_profiles, lbm_objective and lbm_init_rt3_vjp need (bytes).
- * Returns 0 for invalid params.
+ * lbm_profiles, lbm_objective, lbm_init_rt3_vjp and (with diffuse walls)
+ * lbm_step_inplace need (bytes).  Returns 0 for invalid params.
  */
 size_t lbm_scratch_bytes(const lbm_params *params);
 

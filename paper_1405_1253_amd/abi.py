@@ -19,6 +19,7 @@ Q = 37
 MAX_MODES = 32
 F64, F32_DEV = 0, 1
 PERIODIC_Z, NO_COLLIDE, ADJ_F32, WALL_DIFFUSE = 1, 2, 4, 8
+INPLACE_FROM_STATE, INPLACE_FROM_STREAMED = 0, 1
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EALIAS", -3: "LBM_EALIGN",
           -4: "LBM_EHIP", -5: "LBM_ESCRATCH", -6: "LBM_EVERSION"}
@@ -66,6 +67,8 @@ def load():
         P = ctypes.POINTER
         lib.lbm_init_rt3.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP]
         lib.lbm_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
+        lib.lbm_step_inplace.argtypes = [P(lbm_params), _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_size_t,
+                                         _VP]
         lib.lbm_moments.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
         lib.lbm_scratch_bytes.argtypes = [P(lbm_params)]
         lib.lbm_scratch_bytes.restype = ctypes.c_size_t
@@ -80,7 +83,7 @@ def load():
         lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP]
         lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
-        for name in ("lbm_init_rt3", "lbm_step", "lbm_moments", "lbm_lattice", "lbm_objective",
+        for name in ("lbm_init_rt3", "lbm_step", "lbm_step_inplace", "lbm_moments", "lbm_lattice", "lbm_objective",
                      "lbm_adjoint_step", "lbm_init_rt3_vjp", "lbm_profiles"):
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
@@ -157,6 +160,14 @@ def lbm_step(params, ghost, f_in, f_out, moments_out=None, stream=None):
     st = load().lbm_step(ctypes.byref(params), _ptr(ghost), _ptr(f_in), _ptr(f_out),
                          _ptr(moments_out), _stream(stream))
     _check(st, "lbm_step")
+
+
+def lbm_step_inplace(params, ghost, f, kind, moments_out=None, scratch=None, stream=None):
+    """One step on a single buffer, kind INPLACE_FROM_STATE or
+    INPLACE_FROM_STREAMED (see include/lbm.h)."""
+    st = load().lbm_step_inplace(ctypes.byref(params), _ptr(ghost), _ptr(f), int(kind), _ptr(moments_out),
+                                 _ptr(scratch), _nbytes(scratch), _stream(stream))
+    _check(st, "lbm_step_inplace")
 
 
 def lbm_scratch_bytes(params):

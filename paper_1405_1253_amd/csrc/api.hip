@@ -55,6 +55,8 @@ size_t state_bytes(const lbm_params *p) {
 }
 size_t ghost_bytes(const lbm_params *p) { return (size_t)2 * 3 * LBM_Q * elt_size(p->precision); }
 size_t field_bytes(const lbm_params *p) { return (size_t)4 * p->lx * p->lz * sizeof(double); }
+// diffuse-wall M/S of every ghost site for the in-place step: [2 x 3][Lx] double
+size_t wall_ratio_bytes(int lx) { return (size_t)6 * (size_t)lx * sizeof(double); }
 
 // Unperturbed column, rows -3 .. Lz+2, on the host: the density
 // normalisation C and the wall rows.  Same construction as the device
@@ -148,6 +150,7 @@ size_t lbm_scratch_bytes(const lbm_params *p) {
     if (lbm::objective_scratch_bytes(p->lx, p->lz) > b) b = lbm::objective_scratch_bytes(p->lx, p->lz);
     if (vjp_scratch_bytes(p->lx) > b) b = vjp_scratch_bytes(p->lx);
     if (lbm::profiles_scratch_bytes(p->lx, p->lz) > b) b = lbm::profiles_scratch_bytes(p->lx, p->lz);
+    if (wall_ratio_bytes(p->lx) > b) b = wall_ratio_bytes(p->lx);
     return b;
 }
 
@@ -201,7 +204,41 @@ int lbm_step(const lbm_params *p, const void *ghost, const void *f_in, void *f_o
     a.omega = 1.0 / p->tau;
     a.g = p->g;
     a.flags = p->flags;
+    a.ratio = nullptr;
     return hip_status(lbm::launch_step(a, p->precision, (hipStream_t)stream));
+}
+
+int lbm_step_inplace(const lbm_params *p, const void *ghost, void *f, int kind, double *moments_out,
+                     void *scratch, size_t scratch_bytes, lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!f || (kind != LBM_INPLACE_FROM_STATE && kind != LBM_INPLACE_FROM_STREAMED)) return LBM_EINVAL;
+    if (!ghost && !(p->flags & LBM_PERIODIC_Z)) return LBM_EINVAL;
+    const bool diffuse = (p->flags & LBM_WALL_DIFFUSE) != 0;
+    if (!aligned(f, 16) || !aligned(ghost, 8) || !aligned(moments_out, 8) || !aligned(scratch, 8))
+        return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const size_t rb = wall_ratio_bytes(p->lx);
+    if (diffuse && (!scratch || scratch_bytes < rb)) return LBM_ESCRATCH;
+    const size_t sb = state_bytes(p), gb = ghost_bytes(p), fb = field_bytes(p);
+    if (overlap(ghost, gb, f, sb) || overlap(moments_out, fb, f, sb) || overlap(moments_out, fb, ghost, gb) ||
+        (diffuse && (overlap(scratch, rb, f, sb) || overlap(scratch, rb, ghost, gb) ||
+                     overlap(scratch, rb, moments_out, fb))))
+        return LBM_EALIAS;
+    lbm::StepArgs a;
+    a.f_in = nullptr;
+    a.f_out = f;
+    a.ghost = ghost;
+    a.mom = moments_out;
+    a.ratio = diffuse ? static_cast<double *>(scratch) : nullptr;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.tau = p->tau;
+    a.omega = 1.0 / p->tau;
+    a.g = p->g;
+    a.flags = p->flags;
+    return hip_status(lbm::launch_step_inplace(a, p->precision, kind, (hipStream_t)stream));
 }
 
 int lbm_moments(const lbm_params *p, const void *f, double *fields, double *tbar, double *sums,

@@ -12,15 +12,18 @@ enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u, F_WALL_D
 enum : int { P_F64 = 0, P_F32_DEV = 1 };
 
 struct StepArgs {
-    const void *f_in;
-    void *f_out;
+    const void *f_in;    // two-buffer step: input state (unused in place)
+    void *f_out;         // two-buffer step: output state; in place: the buffer
     const void *ghost;   // [2][3][37] elements, unused with F_PERIODIC_Z
     double *mom;         // nullable [4][lx][lz]
+    double *ratio;       // in place with F_WALL_DIFFUSE: scratch [2 x 3][lx]
     int lx, lz;
     double tau, omega, g;
     uint32_t flags;
 };
 hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s);
+// kind 0: the buffer holds the post-collision state, 1: the streamed form
+hipError_t launch_step_inplace(const StepArgs &a, int precision, int kind, hipStream_t s);
 
 struct MomentArgs {
     const void *f;

@@ -22,9 +22,30 @@
 // reading of the bc step of Sec. III.B) gives ghost site s the table row's
 // populations times M(s)/S: M(s) is the mass that streams from the lattice
 // into s in this pull, S the sum of the table row over the populations that
-// point back into the lattice, so s returns exactly what it received.  The
-// block first evaluates M/S for the 2 x 3 x 7 ghost sites its column can
-// pull from (columns x-3..x+3) into LDS.
+// point back into the lattice, so s returns exactly what it received.
+//
+// Single-buffer form (Sec. III.B keeps two lattice copies; this halves the
+// memory).  Two step kinds alternate on one buffer A, each moving the same
+// 37 + 37 elements per site as the two-buffer step:
+//   IN_O: thread x pulls f_l(x) = A[l][x - e_l] (the stored post-collision
+//         state), collides, and writes f*_l(x) to A[-l][x + e_l];
+//   IN_E: thread x reads f_l(x) = A[-l][x], collides, writes f*_l(x) to A[l][x].
+// A thread writes exactly the 37 locations it read (the slots A[m][x - e_m]
+// are the slots A[-l][x + e_l] with m = -l), so no two threads touch the same
+// element and the update is race-free in place.  After IN_O the buffer holds
+// the next step's streamed populations at the opposite slot; after IN_E it
+// holds the post-collision state in the standard layout again.  A population
+// leaving the lattice in IN_O is parked in its own slot A[l][x], which no one
+// else reads or writes in that step (it is the slot a ghost site would fill);
+// in the standard layout the same slots hold the populations that left in
+// the preceding IN_E step.  So in both kinds the mass that streams into a
+// ghost site s is the sum of A[m][s - e_m] over the m leaving the lattice.
+// Launches of an in-place step: (diffuse walls) wall_ratio_kernel saves M/S
+// of every ghost site before those slots are overwritten; step_inplace_kernel
+// steps rows 3..Lz-4 with the interior code only; step_wall_kernel steps the
+// six wall rows per column.  Keeping the wall rows' parking and ghost
+// substitution out of the tile kernel keeps its register count near the
+// two-buffer kernel's (193-195 VGPRs in FP64 instead of 256 with spills).
 #include "common.h"
 #include "kernels.h"
 
@@ -41,89 +62,188 @@ struct Elt<P_F32_DEV> {
     using T = float;
 };
 
+// Addressing of a step: two buffers (pull), or one of the two in-place kinds.
+enum : int { M_PULL = 0, M_IN_O = 1, M_IN_E = 2 };
+
+// Index of -e_l: the rest velocity first, then each +e followed by its -e.
+__host__ __device__ constexpr int opp(int l) { return l == 0 ? 0 : ((l & 1) ? l + 1 : l - 1); }
+constexpr bool opp_is_reversal() {
+    for (int l = 0; l < Q; ++l)
+        if (EX[opp(l)] != -EX[l] || EZ[opp(l)] != -EZ[l]) return false;
+    return true;
+}
+static_assert(opp_is_reversal(), "population order: each +e must be followed by its -e");
+
+// Restrict-qualified pointers only where input and output are distinct.
+template <typename T, bool R>
+struct Ptr {
+    using type = T *;
+};
+template <typename T>
+struct Ptr<T, true> {
+    using type = T *__restrict__;
+};
+
 // Full population value of a state or table element (FP32 stores f - w).
 template <int PREC, typename E>
 __device__ __forceinline__ double full_value(E v, int l) {
     return PREC == P_F64 ? (double)v : (double)v + W[l];
 }
 
-// M/S of the diffuse wall for the ghost sites (side, row i, column x + dx),
-// dx = -3..3, one lane each (lanes 0..41 of a wavefront).
+// M/S of the diffuse wall for ghost site (column xg, row i of a side): M sums
+// the populations f[m] at (xg - e_mx, k - e_mz) that stream into the ghost
+// site from inside the walls, S the table row over the populations that
+// leave the ghost site into the lattice.
 template <int PREC, typename E>
-__device__ __forceinline__ void diffuse_wall_ratios(const StepArgs &a, const E *fin, const E *ghost, int x,
-                                                    int lane, double (*ratio)[3][7]) {
-    if (lane >= 42) return;
+__device__ __forceinline__ double ghost_ratio(const StepArgs &a, const E *f, const E *ghost, int side, int i,
+                                              int xg) {
     const size_t N = (size_t)a.lx * (size_t)a.lz;
-    const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
     const int k = side == 0 ? -1 - i : a.lz + i;
-    const int xg = wrap(x + dx, a.lx);
     const E *row = ghost + (size_t)(side * 3 + i) * Q;
     double M = 0.0, S = 0.0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
-        const int zs = k - EZ[m];   // population m streams from (xg - e_mx, zs) into the ghost site
+        const int zs = k - EZ[m];
         if (zs >= 0 && zs < a.lz) {
             const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
-            M += full_value<PREC>(fin[(size_t)m * N + (size_t)xs * (size_t)a.lz + (size_t)zs], m);
+            M += full_value<PREC>(f[(size_t)m * N + (size_t)xs * (size_t)a.lz + (size_t)zs], m);
         }
-        const int zd = k + EZ[m];   // population m leaves the ghost site towards row zd
+        const int zd = k + EZ[m];
         if (zd >= 0 && zd < a.lz) S += full_value<PREC>(row[m], m);
     }
-    ratio[side][i][dx + 3] = M / S;
+    return M / S;
+}
+
+// M/S for the 2 x 3 x 7 ghost sites (side, row i, column x + dx), dx = -3..3,
+// that column x pulls from, one lane each (lanes 0..41 of a wavefront).
+template <int PREC, typename E>
+__device__ __forceinline__ void diffuse_wall_ratios(const StepArgs &a, const E *fin, const E *ghost, int x,
+                                                    int lane, double (*ratio)[3][7]) {
+    if (lane >= 42) return;
+    const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
+    ratio[side][i][dx + 3] = ghost_ratio<PREC>(a, fin, ghost, side, i, wrap(x + dx, a.lx));
 }
 
 // One site (x, z) of the step.  EDGE: rows within 3 of a wall may pull from
 // ghost sites; lanes with z >= Lz only read (a valid row) and store nothing,
 // nor do lanes with store == false.  DIFFUSE: ghost sites are the diffuse
-// wall's, with M/S from ratio (columns x-3..x+3).
-template <int PREC, bool EDGE, bool DIFFUSE>
+// wall's, with M/S from ratio (columns x-3..x+3).  MODE: addressing (see the
+// file comment); the in-place kinds read and write a.f_out.
+template <int PREC, bool EDGE, bool DIFFUSE, int MODE>
 __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool store,
                                           const double (*ratio)[3][7]) {
     using E = typename Elt<PREC>::T;
+    constexpr bool two = MODE == M_PULL;
     const size_t N = (size_t)a.lx * (size_t)a.lz;
-    const E *__restrict__ fin = static_cast<const E *>(a.f_in);
-    E *__restrict__ fout = static_cast<E *>(a.f_out);
+    typename Ptr<const E, two>::type fin = static_cast<const E *>(two ? a.f_in : a.f_out);
+    typename Ptr<E, two>::type fout = static_cast<E *>(a.f_out);
     const E *__restrict__ ghost = static_cast<const E *>(a.ghost);
     const bool active = store && (!EDGE || z < a.lz);
     const int zq = (EDGE && z >= a.lz) ? a.lz - 1 : z;   // idle lanes read a valid row
     constexpr bool diffuse = EDGE && DIFFUSE;
+    const bool periodic = (a.flags & F_PERIODIC_Z) != 0;
 
-    // ---- propagate + bc: gather the 37 incoming populations -------------
+    // ---- propagate + bc: the incoming population l ------------------------
+    auto gather = [&](int l) -> E {
+        // in-range value: pulled from the neighbour, or (IN_E) this site's -l slot
+        const int xs = (MODE == M_IN_E || EX[l] == 0) ? x : wrap(x - EX[l], a.lx);
+        const E *src = fin + (size_t)(MODE == M_IN_E ? opp(l) : l) * N + (size_t)xs * (size_t)a.lz;
+        const int dz = MODE == M_IN_E ? 0 : EZ[l];
+        if (!EDGE) return src[z - dz];
+        const int zs = zq - EZ[l];   // pull source row: beyond a wall -> ghost site
+        if (diffuse) {
+            if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
+                const int side = zs < 0 ? 0 : 1, i = zs < 0 ? -zs - 1 : zs - a.lz;
+                const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) * ratio[side][i][3 - EX[l]];
+                return (E)(PREC == P_F64 ? f : f - W[l]);
+            }
+            return src[zq - dz];
+        }
+        if (periodic) return src[wrap(zq - dz, a.lz)];
+        if (zs < 0) return ghost[(-zs - 1) * Q + l];
+        if (zs >= a.lz) return ghost[(3 + zs - a.lz) * Q + l];
+        return src[zq - dz];
+    };
+    // All 37 populations are held in registers from the gather to the stores;
+    // in place, a pair's stores overwrite only that pair's own inputs (the
+    // slots of l and -l), which are already in registers.
+    constexpr bool inplace = MODE != M_PULL;
     E v[Q];
+    if (inplace) {
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
-        const int xs = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
-        const E *src = fin + (size_t)l * N + (size_t)xs * (size_t)a.lz;
-        if (!EDGE) {
-            v[l] = src[z - EZ[l]];
-        } else {
-            const int zs = zq - EZ[l];
-            if (diffuse) {
-                if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
-                    const int side = zs < 0 ? 0 : 1, i = zs < 0 ? -zs - 1 : zs - a.lz;
-                    const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) *
-                                     ratio[side][i][3 - EX[l]];
-                    v[l] = (E)(PREC == P_F64 ? f : f - W[l]);
+        for (int l = 0; l < Q; ++l) v[l] = gather(l);
+    } else {
+#pragma unroll
+        for (int l = 0; l < Q; ++l) {
+            const int xs = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
+            const E *src = fin + (size_t)l * N + (size_t)xs * (size_t)a.lz;
+            if (!EDGE) {
+                v[l] = src[z - EZ[l]];
+            } else {
+                const int zs = zq - EZ[l];
+                if (diffuse) {
+                    if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
+                        const int side = zs < 0 ? 0 : 1, i = zs < 0 ? -zs - 1 : zs - a.lz;
+                        const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) *
+                                         ratio[side][i][3 - EX[l]];
+                        v[l] = (E)(PREC == P_F64 ? f : f - W[l]);
+                    } else {
+                        v[l] = src[zs];
+                    }
+                } else if (periodic) {
+                    v[l] = src[wrap(zs, a.lz)];
+                } else if (zs < 0) {
+                    v[l] = ghost[(-zs - 1) * Q + l];
+                } else if (zs >= a.lz) {
+                    v[l] = ghost[(3 + zs - a.lz) * Q + l];
                 } else {
                     v[l] = src[zs];
                 }
-            } else if (a.flags & F_PERIODIC_Z) {
-                v[l] = src[wrap(zs, a.lz)];
-            } else if (zs < 0) {
-                v[l] = ghost[(-zs - 1) * Q + l];
-            } else if (zs >= a.lz) {
-                v[l] = ghost[(3 + zs - a.lz) * Q + l];
-            } else {
-                v[l] = src[zs];
             }
         }
     }
+    auto val = [&](int l) -> E { return v[l]; };
 
     const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
+    // store f*_l of this site: own slot l (two buffers, IN_E), or slot -l of
+    // the site it streams to (IN_O; parked in its own slot l when that site
+    // lies beyond a wall).  The two-buffer step streams its output past the
+    // caches (non-temporal); the in-place kinds store normally, so that the
+    // partial cache lines of IN_O's shifted rows merge in L2 before they are
+    // written back (measured 3 % faster on MI355X).
+    auto put = [&](int l, E val) {
+        if (MODE == M_PULL) {
+            __builtin_nontemporal_store(val, &fout[(size_t)l * N + site]);
+            return;
+        }
+        if (MODE == M_IN_E) {
+            fout[(size_t)l * N + site] = val;
+            return;
+        }
+        const int xd = EX[l] == 0 ? x : wrap(x + EX[l], a.lx);
+        E *dst = fout + (size_t)opp(l) * N + (size_t)xd * (size_t)a.lz;
+        if (!EDGE) {
+            dst[z + EZ[l]] = val;
+        } else {
+            const int zd = z + EZ[l];
+            if (periodic)
+                dst[wrap(zd, a.lz)] = val;
+            else if (zd < 0 || zd >= a.lz)
+                fout[(size_t)l * N + site] = val;
+            else
+                dst[zd] = val;
+        }
+    };
+
     if (a.flags & F_NO_COLLIDE) {
         if (active) {
+            put(0, val(0));
 #pragma unroll
-            for (int l = 0; l < Q; ++l) fout[(size_t)l * N + site] = v[l];
+            for (int l = 1; l < Q; l += 2) {
+                const E p = val(l), m = val(l + 1);
+                put(l, p);
+                put(l + 1, m);
+            }
         }
         return;
     }
@@ -132,7 +252,7 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
     double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const double f = (double)v[l];
+        const double f = (double)val(l);
         s0 += f;
         if (EX[l] != 0) sx += EX[l] * f;
         if (EZ[l] != 0) sz += EZ[l] * f;
@@ -169,18 +289,19 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 if (SHELL[l] != s) continue;
                 if (l == 0) {
                     const double feq = wr * (1.0 + c.a0m1);
-                    if (active) __builtin_nontemporal_store(keep * (double)v[0] + om * feq, &fout[site]);
+                    if (active) put(0, keep * (double)val(0) + om * feq);
                     continue;
                 }
                 if ((l & 1) == 0) continue;   // handled with its +e partner l-1
                 double ev, od;
                 pair_poly<double>(c, R * (EX[l] * vx + EZ[l] * vz), ev, od);
                 const double even = wr * (1.0 + ev), odd = wr * od;
-                const double fp = keep * (double)v[l] + om * (even + odd);
-                const double fm = keep * (double)v[l + 1] + om * (even - odd);
+                const double vp = (double)val(l), vm = (double)val(l + 1);
+                const double fp = keep * vp + om * (even + odd);
+                const double fm = keep * vm + om * (even - odd);
                 if (active) {
-                    __builtin_nontemporal_store(fp, &fout[(size_t)l * N + site]);
-                    __builtin_nontemporal_store(fm, &fout[(size_t)(l + 1) * N + site]);
+                    put(l, fp);
+                    put(l + 1, fm);
                 }
             }
         }
@@ -199,7 +320,8 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 if (SHELL[l] != s) continue;
                 if (l == 0) {
                     const float deq = w * (drho + rhof * c.a0m1);
-                    if (active) __builtin_nontemporal_store(v[0] + om * (deq - v[0]), &fout[site]);
+                    const float v0 = val(0);
+                    if (active) put(0, v0 + om * (deq - v0));
                     continue;
                 }
                 if ((l & 1) == 0) continue;
@@ -207,11 +329,12 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 pair_poly<float>(c, (float)R * ((float)EX[l] * vxf + (float)EZ[l] * vzf), ev, od);
                 const float dp = w * (drho + rhof * (ev + od));
                 const float dm = w * (drho + rhof * (ev - od));
-                const float op = v[l] + om * (dp - v[l]);
-                const float omn = v[l + 1] + om * (dm - v[l + 1]);
+                const float vp = val(l), vm = val(l + 1);
+                const float op = vp + om * (dp - vp);
+                const float omn = vm + om * (dm - vm);
                 if (active) {
-                    __builtin_nontemporal_store(op, &fout[(size_t)l * N + site]);
-                    __builtin_nontemporal_store(omn, &fout[(size_t)(l + 1) * N + site]);
+                    put(l, op);
+                    put(l + 1, omn);
                 }
             }
         }
@@ -235,9 +358,10 @@ struct StepShape<P_F32_DEV> {
     static constexpr int BS = 256, ZT = 2;
 };
 
-// Diffuse-wall rows of one column per wavefront.  Lanes 0..41 evaluate M/S
-// of the 2 x 3 x 7 ghost sites the column pulls from, then lane j < min(Lz, 6)
-// steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row when Lz < 6).
+// Diffuse-wall rows of one column per wavefront (two-buffer step).  Lanes
+// 0..41 evaluate M/S of the 2 x 3 x 7 ghost sites the column pulls from, then
+// lane j < min(Lz, 6) steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every
+// row when Lz < 6).
 template <int PREC, int BS>
 __device__ __forceinline__ void wall_block(const StepArgs &a, uint32_t b) {
     using E = typename Elt<PREC>::T;
@@ -252,7 +376,7 @@ __device__ __forceinline__ void wall_block(const StepArgs &a, uint32_t b) {
     __syncthreads();
     const int nw = a.lz < 6 ? a.lz : 6;
     if (live && lane < nw)
-        step_site<PREC, true, true>(a, x, lane < 3 ? lane : a.lz - (nw - lane), true, ratio[w]);
+        step_site<PREC, true, true, M_PULL>(a, x, lane < 3 ? lane : a.lz - (nw - lane), true, ratio[w]);
 }
 
 // One launch per step.  With diffuse walls the first nwall blocks step the
@@ -277,10 +401,65 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, i
         const int z = z0 + (int)threadIdx.x;
         const bool edge = (z0 < 3) || (z0 + BS + 3 > a.lz);
         if (edge)
-            step_site<PREC, true, false>(a, x, z, !skip_wall || (z >= 3 && z < a.lz - 3), nullptr);
+            step_site<PREC, true, false, M_PULL>(a, x, z, !skip_wall || (z >= 3 && z < a.lz - 3), nullptr);
         else
-            step_site<PREC, false, false>(a, x, z, true, nullptr);
+            step_site<PREC, false, false, M_PULL>(a, x, z, true, nullptr);
     }
+}
+
+// In-place kinds, rows 3 .. Lz-4 (every source and destination inside the
+// walls): only the branch-free interior code, which keeps the kernel's
+// register count at the two-buffer level; in tiles that reach a wall the
+// lanes outside these rows load a valid row and store nothing.  The wall rows
+// are stepped by step_wall_kernel.
+template <int PREC, int MODE>
+__global__ __launch_bounds__(StepShape<PREC>::BS) void step_inplace_kernel(StepArgs a, int nzb) {
+    constexpr int BS = StepShape<PREC>::BS, ZT = StepShape<PREC>::ZT;
+    const int x = (int)(blockIdx.x / (uint32_t)nzb);
+    const int zt = (int)(blockIdx.x % (uint32_t)nzb) * ZT;
+    for (int k = 0; k < ZT; ++k) {
+        const int z0 = (zt + k) * BS;
+        if (z0 >= a.lz) break;
+        const int z = z0 + (int)threadIdx.x;
+        const bool inner = z >= 3 && z < a.lz - 3;
+        const int zc = z < 3 ? 3 : (z > a.lz - 4 ? a.lz - 4 : z);
+        step_site<PREC, false, false, MODE>(a, x, zc, inner, nullptr);
+    }
+}
+
+// In-place kinds: the wall rows (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row
+// when Lz < 7), one wavefront per column, with the Dirichlet table or the
+// diffuse wall's M/S from a.ratio (wall_ratio_kernel).
+template <int PREC, int MODE, bool DIFFUSE>
+__global__ __launch_bounds__(256) void step_wall_kernel(StepArgs a) {
+    constexpr int NW = 4;   // columns per block
+    __shared__ double ratio[NW][2][3][7];
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const int x = __builtin_amdgcn_readfirstlane((int)blockIdx.x * NW + w);
+    const bool live = x < a.lx;
+    if (DIFFUSE) {
+        if (live && lane < 42) {
+            const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
+            ratio[w][side][i][dx + 3] = a.ratio[(size_t)(side * 3 + i) * a.lx + wrap(x + dx, a.lx)];
+        }
+        __syncthreads();
+    }
+    const int nw = a.lz < 7 ? a.lz : 6;
+    if (live && lane < nw)
+        step_site<PREC, true, DIFFUSE, MODE>(a, x, lane < 3 || a.lz < 7 ? lane : a.lz - (nw - lane), true,
+                                             DIFFUSE ? ratio[w] : nullptr);
+}
+
+// In-place kinds with diffuse walls: M/S of every ghost site into a.ratio
+// ([2 x 3][Lx]) before the step overwrites the slots the masses are read from.
+template <int PREC>
+__global__ __launch_bounds__(256) void wall_ratio_kernel(StepArgs a) {
+    using E = typename Elt<PREC>::T;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= 6 * a.lx) return;
+    const int row = t / a.lx, xg = t % a.lx;
+    a.ratio[t] = ghost_ratio<PREC>(a, static_cast<const E *>(a.f_out), static_cast<const E *>(a.ghost), row / 3,
+                                   row % 3, xg);
 }
 
 template <int PREC>
@@ -292,11 +471,44 @@ static void launch_prec(const StepArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(step_kernel<PREC>, dim3(nwall + nblocks), dim3(BS), 0, s, a, nzb, nblocks, nwall);
 }
 
+template <int PREC, int MODE>
+static void launch_inplace(const StepArgs &a, hipStream_t s) {
+    constexpr int BS = StepShape<PREC>::BS, span = BS * StepShape<PREC>::ZT;
+    const bool diffuse = (a.flags & F_WALL_DIFFUSE) != 0;
+    if (diffuse)
+        hipLaunchKernelGGL(wall_ratio_kernel<PREC>, dim3((uint32_t)((6 * a.lx + 255) / 256)), dim3(256), 0, s, a);
+    if (a.lz >= 7) {
+        const int nzb = (a.lz + span - 1) / span;
+        hipLaunchKernelGGL((step_inplace_kernel<PREC, MODE>), dim3((uint32_t)nzb * (uint32_t)a.lx), dim3(BS), 0, s,
+                           a, nzb);
+    }
+    const dim3 wgrid((uint32_t)((a.lx + 3) / 4));
+    if (diffuse)
+        hipLaunchKernelGGL((step_wall_kernel<PREC, MODE, true>), wgrid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((step_wall_kernel<PREC, MODE, false>), wgrid, dim3(256), 0, s, a);
+}
+
 hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s) {
     if (precision == P_F64)
         launch_prec<P_F64>(a, s);
     else
         launch_prec<P_F32_DEV>(a, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_inplace(const StepArgs &a, int precision, int kind, hipStream_t s) {
+    if (precision == P_F64) {
+        if (kind == 0)
+            launch_inplace<P_F64, M_IN_O>(a, s);
+        else
+            launch_inplace<P_F64, M_IN_E>(a, s);
+    } else {
+        if (kind == 0)
+            launch_inplace<P_F32_DEV, M_IN_O>(a, s);
+        else
+            launch_inplace<P_F32_DEV, M_IN_E>(a, s);
+    }
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 """Lattice: device buffers and stream plumbing around the C entry points.
 
-Owns the prv/nxt pair of population buffers (Sec. III.B), the wall table and
-the diagnostics scratch, all as torch tensors on one GPU; every computation is
-a call into liblbm.so on the current torch stream.
+Owns the prv/nxt pair of population buffers (Sec. III.B) -- or, with
+``inplace=True``, a single buffer stepped by lbm_step_inplace -- the wall
+table and the diagnostics scratch, all as torch tensors on one GPU; every
+computation is a call into liblbm.so on the current torch stream.
 """
 import numpy as np
 import torch
@@ -12,7 +13,7 @@ from .workload import Workload, draw_modes
 
 
 class Lattice:
-    def __init__(self, lx, lz, tau, g, precision="f64", flags=0, device="cuda"):
+    def __init__(self, lx, lz, tau, g, precision="f64", flags=0, device="cuda", inplace=False):
         if precision not in ("f64", "f32dev"):
             raise ValueError(precision)
         self.lx, self.lz, self.tau, self.g = lx, lz, tau, g
@@ -21,9 +22,11 @@ class Lattice:
         self.params = abi.make_params(lx, lz, tau, g,
                                       abi.F64 if precision == "f64" else abi.F32_DEV, flags)
         self.device = torch.device(device)
+        self.inplace = inplace
         self.buf = [torch.empty((abi.Q, lx, lz), dtype=self.dtype, device=self.device)
-                    for _ in range(2)]
+                    for _ in range(1 if inplace else 2)]
         self.cur = 0
+        self.kind = abi.INPLACE_FROM_STATE   # in place: what the buffer holds
         self.ghost = torch.zeros((2, 3, abi.Q), dtype=self.dtype, device=self.device)
         nbytes = max(abi.lbm_scratch_bytes(self.params), 256)
         self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -33,6 +36,7 @@ class Lattice:
     @classmethod
     def from_workload(cls, wl: Workload, modes=None, amp=None, device="cuda", **kw):
         kw["flags"] = kw.get("flags", 0) | abi.wall_flag(wl.wall)
+        kw.setdefault("inplace", wl.inplace)
         lat = cls(wl.lx, wl.lz, wl.tau, wl.g, precision=wl.precision, device=device, **kw)
         modes = modes if modes is not None else draw_modes(wl.seed)
         a = modes.amp if amp is None else amp
@@ -49,24 +53,33 @@ class Lattice:
         self.diag_desc = self.desc     # temperatures of the tent-map diagnostics
         abi.lbm_init_rt3(self.params, self.desc, amp, self.buf[0], self.ghost)
         self.cur = 0
+        self.kind = abi.INPLACE_FROM_STATE
         self.steps_done = 0
         self._amp = amp   # keep alive until the stream has consumed it
 
     # ---- time stepping ----------------------------------------------------
     @property
     def state(self):
+        if self.kind != abi.INPLACE_FROM_STATE:
+            raise RuntimeError("the single buffer holds the streamed form after an odd number of "
+                               "in-place steps; step once more to get the post-collision state")
         return self.buf[self.cur]
 
     def set_state(self, f):
         self.buf[self.cur].copy_(f)
+        self.kind = abi.INPLACE_FROM_STATE
 
     def step(self, n=1, moments_out=None):
         """Advance n steps; moments_out (optional) receives the last step's
         pre-collision moments [4, lx, lz]."""
         for i in range(n):
             mo = moments_out if i == n - 1 else None
-            abi.lbm_step(self.params, self.ghost, self.buf[self.cur], self.buf[1 - self.cur], mo)
-            self.cur = 1 - self.cur
+            if self.inplace:
+                abi.lbm_step_inplace(self.params, self.ghost, self.buf[0], self.kind, mo, self.scratch)
+                self.kind ^= 1
+            else:
+                abi.lbm_step(self.params, self.ghost, self.buf[self.cur], self.buf[1 - self.cur], mo)
+                self.cur = 1 - self.cur
         self.steps_done += n
 
     # ---- diagnostics ------------------------------------------------------
@@ -120,6 +133,7 @@ class Lattice:
         lat.buf[0].copy_(d["state"])
         lat.ghost.copy_(d["ghost"])
         lat.cur = 0
+        lat.kind = abi.INPLACE_FROM_STATE
         lat.steps_done = d["steps_done"]
         return lat
 

@@ -49,6 +49,7 @@ class Workload:
     t_m_diag: float = None    # middle temperature of the tent-map diagnostics
                               # (the single-front run's "virtual" T_m)
     wall: str = "dirichlet"   # wall rule: "dirichlet" or "diffuse" (mass-conserving)
+    inplace: bool = False     # single population buffer (lbm_step_inplace)
 
     @property
     def g(self) -> float:
@@ -73,6 +74,8 @@ WORKLOADS = {
         Workload("rt3_4096x12288_f32_diffuse", 4096, 12288, 20000, "f32dev", 1405, wall="diffuse"),
         Workload("rt3_512x1536_adj_diffuse", 512, 1536, 2000, "f64", 1253, ckpt_every=100,
                  wall="diffuse"),
+        Workload("rt3_4096x12288_inplace", 4096, 12288, 1000, "f64", 1405, inplace=True),
+        Workload("rt3_4096x12288_f32_inplace", 4096, 12288, 20000, "f32dev", 1405, inplace=True),
         Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250,
                  adj_precision="f32"),
         # The runs of Sec. IV, Table II: 2400 x 6144, g = 1.5e-5, T 1.025/1/0.975,

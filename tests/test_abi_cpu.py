@@ -79,6 +79,29 @@ def test_step_rejects_bad_arguments(abi):
     assert _call_step(abi, mk(16, 16, 0.7, 0.0), mom=(2 << 30) + 4096) == -2
 
 
+def test_step_inplace_rejects_bad_arguments(abi):
+    lib = abi.load()
+    mk = abi.make_params
+    p = mk(16, 16, 0.7, 0.0)
+    f, gh, mom = 2 << 30, 1 << 20, 3 << 30
+
+    def call(params, ghost=gh, f=f, kind=0, mom=None, scratch=None, nbytes=0):
+        return lib.lbm_step_inplace(ctypes.byref(params), ghost, f, kind, mom, scratch, nbytes, None)
+
+    assert call(p, kind=2) == -1
+    assert call(p, f=None) == -1
+    assert call(p, ghost=None) == -1                          # walls need a table
+    assert call(p, f=f + 8) == -3
+    assert call(p, mom=f + 4096) == -2                        # moments inside the state
+    pd = mk(16, 16, 0.7, 0.0, flags=abi.WALL_DIFFUSE)
+    assert call(pd) == -5                                     # diffuse walls need scratch
+    need = abi.lbm_scratch_bytes(pd)
+    assert need >= 6 * 16 * 8
+    assert call(pd, scratch=4 << 30, nbytes=6 * 16 * 8 - 8) == -5
+    assert call(pd, scratch=f + 64, nbytes=need) == -2        # scratch inside the state
+    assert call(mk(0, 16, 0.7, 0.0)) == 0                     # empty lattice
+
+
 def test_empty_lattice_is_a_no_op(abi):
     for lx, lz in ((0, 16), (16, 0)):
         assert _call_step(abi, abi.make_params(lx, lz, 0.7, 0.0)) == 0

@@ -1,0 +1,164 @@
+"""Single-buffer step (lbm_step_inplace) against the two-buffer step and the
+oracle.
+
+Bars: streaming only, the streamed form after one step is the layout
+include/lbm.h defines and two steps equal two two-buffer steps, bit for bit;
+with collisions the two in-place kinds in turn give, after every even number
+of steps, the two-buffer state to rounding (the same formulas per site; the
+compiler may contract them to FMAs differently in the two instantiations):
+1e-13 relative in FP64, 2^-20 of the largest deviation in FP32, moments to
+1e-13 (FP64) / 1e-6 (FP32) absolute, and the oracle within 1e-12 (FP64);
+both wall rules, both precisions, periodic z, ragged and tiny lattices.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lbm as O
+from oracle.lattice import lattice
+from paper_1405_1253_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_1405_1253_amd import abi as mod
+    mod.load()
+    return mod
+
+
+def _opp():
+    E = lattice()[0]
+    return [int(np.nonzero((E[:, 0] == -E[l, 0]) & (E[:, 1] == -E[l, 1]))[0][0]) for l in range(37)]
+
+
+def _scratch(abi, params):
+    return torch.empty(max(abi.lbm_scratch_bytes(params), 256), dtype=torch.uint8, device=DEV)
+
+
+def _two_buffer(abi, params, ghost, f0, steps, mom=False):
+    fa, fb = f0.clone(), torch.empty_like(f0)
+    moms = []
+    for _ in range(steps):
+        m = torch.empty((4, params.lx, params.lz), dtype=torch.float64, device=DEV) if mom else None
+        abi.lbm_step(params, ghost, fa, fb, m)
+        fa, fb = fb, fa
+        moms.append(m)
+    return fa, moms
+
+
+def _in_place(abi, params, ghost, f0, steps, mom=False):
+    f = f0.clone()
+    scratch = _scratch(abi, params)
+    moms = []
+    for t in range(steps):
+        m = torch.empty((4, params.lx, params.lz), dtype=torch.float64, device=DEV) if mom else None
+        abi.lbm_step_inplace(params, ghost, f, t % 2, m, scratch)
+        moms.append(m)
+    return f, moms
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32dev"])
+@pytest.mark.parametrize("mode", ["dirichlet", "diffuse", "periodic"])
+@pytest.mark.parametrize("lx,lz", [(64, 200), (37, 300), (5, 7), (2, 3)])
+def test_streaming_in_place(abi, prec, mode, lx, lz):
+    """Streaming only: after one step the buffer holds the streamed form of
+    include/lbm.h; after two it equals two two-buffer steps, bit for bit."""
+    dt = np.float64 if prec == "f64" else np.float32
+    f = W.random_populations(500 + lx, lx, lz).astype(dt)
+    ghost = W.random_ghost(600 + lz).astype(dt)
+    flags = abi.NO_COLLIDE | {"dirichlet": 0, "diffuse": abi.WALL_DIFFUSE, "periodic": abi.PERIODIC_Z}[mode]
+    params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F64 if prec == "f64" else abi.F32_DEV, flags)
+    f0, gh = torch.as_tensor(f, device=DEV), torch.as_tensor(ghost, device=DEV)
+    one, _ = _in_place(abi, params, gh, f0, 1)
+    pulled, _ = _two_buffer(abi, params, gh, f0, 1)
+    got, g = one.cpu().numpy(), pulled.cpu().numpy()
+    E, opp = lattice()[0], _opp()
+    want = np.empty_like(got)
+    for l in range(37):
+        # the step's output g, streamed once more: slot -l at x holds g_l(x - e_l)
+        ex, ez = int(E[l, 0]), int(E[l, 1])
+        want[opp[l]] = np.roll(g[l], shift=(ex, ez), axis=(0, 1))
+        if mode == "periodic":
+            continue
+        # rows whose source lies beyond a wall hold the parked population -l
+        for z in range(lz):
+            if not 0 <= z - ez < lz:
+                want[opp[l], :, z] = g[opp[l], :, z]
+    assert np.array_equal(got, want)
+    two, _ = _in_place(abi, params, gh, f0, 2)
+    ref, _ = _two_buffer(abi, params, gh, f0, 2)
+    assert torch.equal(two, ref)
+
+
+def _init(abi, params, seed, width=4.0, nmodes=16):
+    m = W.draw_modes(seed, nmodes)
+    dt = torch.float64 if params.precision == abi.F64 else torch.float32
+    f = torch.empty((37, params.lx, params.lz), dtype=dt, device=DEV)
+    gh = torch.empty((2, 3, 37), dtype=dt, device=DEV)
+    abi.lbm_init_rt3(params, abi.RT3Desc(1.05, 1.0, 0.95, width, m.k, m.phase),
+                     torch.as_tensor(m.amp, device=DEV), f, gh)
+    return m, f, gh
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32dev"])
+@pytest.mark.parametrize("wall", ["dirichlet", "diffuse"])
+def test_in_place_equals_two_buffers(abi, prec, wall):
+    """128 x 384 three-layer workload, 2 and 20 steps: the two-buffer state
+    and moments_out of every step, to rounding."""
+    params = abi.make_params(128, 384, 0.7, 2.6e-4, abi.F64 if prec == "f64" else abi.F32_DEV,
+                             abi.wall_flag(wall))
+    _, f0, gh = _init(abi, params, 1405)
+    for steps in (2, 20):
+        a, ma = _in_place(abi, params, gh, f0, steps, mom=True)
+        b, mb = _two_buffer(abi, params, gh, f0, steps, mom=True)
+        a, b = a.double(), b.double()
+        if prec == "f64":
+            err = float(((a - b).abs() / b.abs()).max())
+            bar = 1e-13
+        else:   # deviations f - w: relative to the largest one
+            err = float((a - b).abs().max() / b.abs().max())
+            bar = 2.0 ** -20
+        # absolute: rho and T are ~1, the velocities ~1e-4 (their relative
+        # rounding is amplified by the cancellation in sum_l xi_l f_l)
+        merr = max(float((x - y).abs().max()) for x, y in zip(ma[1:], mb[1:]))
+        print(f"{prec} {wall}, {steps} steps: in place vs two buffers: state {err:.2e}, "
+              f"moments {merr:.2e}, first step's moments equal: {torch.equal(ma[0], mb[0])}")
+        assert err <= bar, (steps, err)
+        assert torch.equal(ma[0], mb[0])         # same input, same moment sums
+        assert merr <= (1e-13 if prec == "f64" else 1e-6), (steps, merr)
+
+
+def test_in_place_parity_with_oracle_ragged_and_tiny(abi):
+    for lx, lz, steps, width, wall in ((37, 300, 12, 4.0, "dirichlet"), (37, 300, 12, 4.0, "diffuse"),
+                                       (2, 3, 4, 1.0, "diffuse"), (4, 6, 4, 1.0, "dirichlet"),
+                                       (1, 1, 2, 1.0, "diffuse")):
+        params = abi.make_params(lx, lz, 0.6, 3e-4, flags=abi.wall_flag(wall))
+        m, f0, gh = _init(abi, params, 7, width=width, nmodes=2)
+        p = O.Params(lx, lz, 0.6, 3e-4, wall=wall)
+        f_o, ghost_o = O.init_rt3(p, O.RT3(1.05, 1.0, 0.95, width, m.k, m.phase), m.amp)
+        want = O.run(f_o, ghost_o, p, steps)
+        got, _ = _in_place(abi, params, gh, f0, steps)
+        err = float(np.max(np.abs(got.cpu().numpy() - want) / want))
+        assert err <= 1e-12, (lx, lz, wall, err)
+
+
+def test_lattice_in_place_runtime(abi):
+    """Lattice(inplace=True): one buffer; the state is readable after an even
+    number of steps and refused after an odd one."""
+    from paper_1405_1253_amd.runtime import Lattice
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    lat = Lattice.from_workload(wl, modes=m, inplace=True)
+    ref = Lattice.from_workload(wl, modes=m)
+    assert len(lat.buf) == 1
+    lat.step(3)
+    with pytest.raises(RuntimeError):
+        lat.sums()
+    lat.step(1)
+    ref.step(4)
+    assert float(((lat.state - ref.state).abs() / ref.state.abs()).max()) <= 1e-13
+    a, b = lat.sums(), ref.sums()              # mass, momentum (~0 in x), energy
+    assert float((a - b).abs().max()) <= 1e-12 * float(b[0])
