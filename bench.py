@@ -102,9 +102,13 @@ def cpu_baseline(wl, columns=32, min_seconds=10.0, max_steps=64):
 def adjoint_ratio(name, budget_bytes=None, warm=True):
     """Wall time of the rollout's forward pass (with checkpoints and stored
     moments) and of its backward pass (recomputation + adjoint sweep + init
-    VJP), against a plain forward of the same steps (one run each, after one
-    warm-up run of every phase if ``warm``)."""
+    VJP), against a plain forward of the same steps: the plain forward is
+    timed twice after a warm-up (the mean is the reference), the rollout once
+    (after one warm-up run of every phase if ``warm``).  Also the adjoint step
+    alone (20 launches on the rollout's buffers, HIP events) with its HBM
+    bandwidth at 37 x 2 adjoint elements + 4 moments per site."""
     import torch
+    from paper_1405_1253_amd import abi
     from paper_1405_1253_amd.rollout import Rollout, RolloutConfig
     from paper_1405_1253_amd.runtime import Lattice
     from paper_1405_1253_amd.workload import WORKLOADS, draw_modes
@@ -121,8 +125,8 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
         return time.perf_counter() - t0, out
 
     lat = Lattice.from_workload(wl, modes=m)
-    lat.step(wl.steps if warm else 2)                   # warm-up
-    t_plain, _ = timed(lambda: lat.step(wl.steps))
+    lat.step(wl.steps if warm else 200)                 # warm-up
+    t_plain = [timed(lambda: lat.step(wl.steps))[0] for _ in range(2)]
     del lat
     torch.cuda.empty_cache()
     r = Rollout(RolloutConfig.from_workload(wl, m, **kw))
@@ -132,13 +136,32 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
     r.recomputed_steps = 0
     t_fwd, _ = timed(lambda: r.forward(amp))
     t_bwd, grad = timed(r.backward)
-    out = {"workload": name, "steps": wl.steps, "plain_forward_s": round(t_plain, 4),
+    plain = sum(t_plain) / len(t_plain)
+
+    # the adjoint step alone, on the rollout's buffers
+    mom = r.kept[0] if r.keep else r.segbuf[0]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    abi.lbm_adjoint_step(r.params, r.ghost, mom, r.lam[0], r.lam[1])
+    e0.record(stream)
+    for i in range(20):
+        abi.lbm_adjoint_step(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_adj = e0.elapsed_time(e1) / 20 / 1e3
+    site_bytes = 2 * abi.Q * r.lam[0].element_size() + 4 * mom.element_size()
+    adj_gbs = site_bytes * wl.lx * wl.lz / t_adj / 1e9
+    out = {"workload": name, "steps": wl.steps, "plain_forward_s": [round(t, 4) for t in t_plain],
            "rollout_forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4),
-           "backward_over_plain_forward": round(t_bwd / t_plain, 3),
-           "gradient_over_plain_forward": round((t_fwd + t_bwd) / t_plain, 3),
+           "backward_over_plain_forward": round(t_bwd / plain, 3),
+           "gradient_over_plain_forward": round((t_fwd + t_bwd) / plain, 3),
            "recomputed_steps": r.recomputed_steps, "moments_kept": r.keep,
+           "moments_dtype": str(mom.dtype).replace("torch.", ""),
+           "adjoint_step_ms": round(t_adj * 1e3, 4),
+           "adjoint_step_over_forward_step": round(t_adj / (plain / wl.steps), 3),
+           "adjoint_hbm_gbs": round(adj_gbs, 1), "adjoint_frac": round(adj_gbs / HBM_PEAK_GBS, 4),
            "grad_finite": bool(torch.isfinite(grad).all().item())}
-    del r
+    del r, mom
     torch.cuda.empty_cache()
     return out
 
@@ -233,7 +256,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = [adjoint_ratio("rt3_512x1536_adj"),
                           adjoint_ratio("rt3_512x1536_adj_diffuse"),
-                          adjoint_ratio("rt3_2048x6144_adj", 60 << 30, warm=False)]
+                          adjoint_ratio("rt3_2048x6144_adj", 212 << 30, warm=False)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -86,8 +86,10 @@ enum lbm_flags {
     LBM_NO_COLLIDE = 2u, /* test mode: streaming and walls only                          */
     LBM_ADJ_F32 = 4u,    /* adjoint buffers (lam_seed, lam_in/lam_out, lam0) are float,
                             not double; the adjoint arithmetic stays double            */
-    LBM_WALL_DIFFUSE = 8u /* mass-conserving diffuse walls instead of Dirichlet walls
+    LBM_WALL_DIFFUSE = 8u, /* mass-conserving diffuse walls instead of Dirichlet walls
                             (lbm_step); not with LBM_PERIODIC_Z                       */
+    LBM_MOM_F32 = 16u     /* the step's moments_out and the adjoint's moments are float
+                            [4][Lx][Lz] (half the memory of stored adjoint moments)   */
 };
 
 typedef struct lbm_params {
@@ -167,8 +169,9 @@ int lbm_init_rt3(const lbm_params *params, const lbm_rt3_desc *desc, const doubl
  *   ghost        (device) wall table [2][3][37]; may be NULL with LBM_PERIODIC_Z
  *   f_in         (device) state buffer, read
  *   f_out        (device) state buffer, written; must not overlap f_in
- *   moments_out  (device, nullable) double [4][Lx][Lz]: rho, u_x, u_z, T of g
- *                (the pre-collision moments of this step, not renormalised)
+ *   moments_out  (device, nullable) double [4][Lx][Lz] (float with LBM_MOM_F32):
+ *                rho, u_x, u_z, T of g (the pre-collision moments of this step,
+ *                not renormalised)
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
  */
 int lbm_step(const lbm_params *params, const void *ghost, const void *f_in, void *f_out,
@@ -294,8 +297,9 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  *
  *   ghost    (device) the wall table the forward step used; required with
  *            LBM_WALL_DIFFUSE, otherwise unused and may be NULL
- *   moments  (device) double [4][Lx][Lz]: rho, u_x, u_z, T written by the
- *            forward lbm_step's moments_out (may be NULL with LBM_NO_COLLIDE)
+ *   moments  (device) double [4][Lx][Lz] (float with LBM_MOM_F32): rho, u_x,
+ *            u_z, T written by the forward lbm_step's moments_out (may be NULL
+ *            with LBM_NO_COLLIDE)
  *   lam_in   (device) [37][Lx][Lz], double (float with LBM_ADJ_F32)
  *   lam_out  (device) same type and shape, must not overlap lam_in, moments
  *            or ghost

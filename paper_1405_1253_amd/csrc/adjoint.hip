@@ -62,13 +62,14 @@ struct EqVjp {
     double sp, sxx, sxz, su2, sth;
 };
 
-__device__ __forceinline__ EqVjp eq_vjp_sums(const double lam[Q], double vx, double vz, double th) {
+template <typename LT>
+__device__ __forceinline__ EqVjp eq_vjp_sums(const LT lam[Q], double vx, double vz, double th) {
     // m[p][q]: p powers of xi_x, q of xi_z
     double m00 = 0, m10 = 0, m01 = 0, m20 = 0, m11 = 0, m02 = 0, m30 = 0, m21 = 0, m12 = 0, m03 = 0;
     double m40 = 0, m31 = 0, m22 = 0, m13 = 0, m04 = 0;
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const double lw = lam[l] * W[l];
+        const double lw = (double)lam[l] * W[l];
         const double a = R * EX[l], b = R * EZ[l];
         m00 += lw;
         if (EX[l] != 0) {
@@ -128,7 +129,7 @@ __device__ __forceinline__ EqVjp eq_vjp_sums(const double lam[Q], double vx, dou
 // ---------------------------------------------------------------------------
 // adjoint step
 // ---------------------------------------------------------------------------
-template <bool EDGE, typename L>
+template <bool EDGE, typename L, typename MT>
 __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0) {
     const L *__restrict__ lam_in = static_cast<const L *>(a.lam_in);
     L *__restrict__ lam_out = static_cast<L *>(a.lam_out);
@@ -137,19 +138,18 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
     if (EDGE && z >= a.lz) return;
     const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
     // uniform column base + 32-bit per-lane byte offset for every access
-    const uint32_t zoff = (uint32_t)z * 8u;
     const uint32_t loff = (uint32_t)z * (uint32_t)sizeof(L);
-    double lam[Q];
+    L lam[Q];   // held in the buffer's type (float buffers: half the registers)
 #pragma unroll
-    for (int l = 0; l < Q; ++l)
-        lam[l] = (double)ldg_off(lam_in + (size_t)l * N + (size_t)x * (size_t)a.lz, loff);
+    for (int l = 0; l < Q; ++l) lam[l] = ldg_off(lam_in + (size_t)l * N + (size_t)x * (size_t)a.lz, loff);
 
     // G_l = keep lam_l + alpha + beta . xi_l + gamma |xi_l|^2 (NO_COLLIDE: G = lam)
     double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
     if (!(a.flags & F_NO_COLLIDE)) {
-        const double *mcol = a.mom + (size_t)x * (size_t)a.lz;
-        const double rho = ldg_off(mcol, zoff), ux = ldg_off(mcol + N, zoff),
-                     uz = ldg_off(mcol + 2 * N, zoff), T = ldg_off(mcol + 3 * N, zoff);
+        const MT *mcol = static_cast<const MT *>(a.mom) + (size_t)x * (size_t)a.lz;
+        const uint32_t moff = (uint32_t)z * (uint32_t)sizeof(MT);
+        const double rho = ldg_off(mcol, moff), ux = ldg_off(mcol + N, moff),
+                     uz = ldg_off(mcol + 2 * N, moff), T = ldg_off(mcol + 3 * N, moff);
         const double vx = ux, vz = uz - a.tau * a.g;
         const double th = T + a.tau * (1.0 - a.tau) * a.g * a.g / D - 1.0;
         const EqVjp s = eq_vjp_sums(lam, vx, vz, th);
@@ -168,7 +168,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
 
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const L G = (L)(keep * lam[l] + alpha + (EX[l] * bx + EZ[l] * bz) + gamma * XI2_SHELL[SHELL[l]]);
+        const L G = (L)(keep * (double)lam[l] + alpha + (EX[l] * bx + EZ[l] * bz) + gamma * XI2_SHELL[SHELL[l]]);
         const int xd = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
         const int zd = z - EZ[l];
         L *dst = lam_out + (size_t)l * N + (size_t)xd * (size_t)a.lz;
@@ -186,7 +186,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
                 L park = L(0);
                 if (a.flags & F_WALL_DIFFUSE) {
                     const int o = l == 0 ? 0 : ((l & 1) ? l + 1 : l - 1);   // -e_l
-                    park = (L)(keep * lam[o] + alpha + (EX[o] * bx + EZ[o] * bz) +
+                    park = (L)(keep * (double)lam[o] + alpha + (EX[o] * bx + EZ[o] * bz) +
                                gamma * XI2_SHELL[SHELL[o]]);
                 }
                 lam_out[(size_t)l * N + site] = park;
@@ -195,14 +195,45 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
     }
 }
 
-template <typename L>
-__global__ __launch_bounds__(BLOCK) void adjoint_step_kernel(AdjointArgs a, int nzb) {
+#ifndef LBM_ADJ_BS
+#define LBM_ADJ_BS 256
+#endif
+#ifndef LBM_ADJ_ZT
+#define LBM_ADJ_ZT 1
+#endif
+constexpr int ADJ_BS = LBM_ADJ_BS, ADJ_ZT = LBM_ADJ_ZT;
+
+// L: element type of the adjoint buffers; MT: of the stored moments
+// Occupancy target: 3 wavefronts per SIMD with float buffers and float
+// moments (168 VGPRs, a few bytes of spills), 2 otherwise (165-179 VGPRs);
+// measured fastest on MI355X for the 2048 x 6144 float rollout and the
+// 512 x 1536 double rollout respectively.
+template <typename L, typename MT>
+struct AdjWaves {
+    static constexpr int value = (sizeof(L) == 4 && sizeof(MT) == 4) ? 3 : 2;
+};
+
+template <typename L, typename MT>
+__global__ __launch_bounds__(ADJ_BS) __attribute__((amdgpu_waves_per_eu(AdjWaves<L, MT>::value)))
+void adjoint_step_kernel(AdjointArgs a, int nzb) {
     const int x = (int)(blockIdx.x / (uint32_t)nzb);
-    const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BLOCK;
-    if ((z0 < 3) || (z0 + BLOCK + 3 > a.lz))
-        adjoint_tile<true, L>(a, x, z0);
-    else
-        adjoint_tile<false, L>(a, x, z0);
+    if (ADJ_ZT == 1) {
+        const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * ADJ_BS;
+        if ((z0 < 3) || (z0 + ADJ_BS + 3 > a.lz))
+            adjoint_tile<true, L, MT>(a, x, z0);
+        else
+            adjoint_tile<false, L, MT>(a, x, z0);
+        return;
+    }
+    const int zt = (int)(blockIdx.x % (uint32_t)nzb) * ADJ_ZT;
+    for (int k = 0; k < ADJ_ZT; ++k) {
+        const int z0 = (zt + k) * ADJ_BS;
+        if (z0 >= a.lz) break;
+        if ((z0 < 3) || (z0 + ADJ_BS + 3 > a.lz))
+            adjoint_tile<true, L, MT>(a, x, z0);
+        else
+            adjoint_tile<false, L, MT>(a, x, z0);
+    }
 }
 
 // Diffuse wall, second pass: one thread per ghost site (x_g, row k), reading
@@ -240,13 +271,18 @@ __global__ __launch_bounds__(BLOCK) void adjoint_wall_kernel(AdjointArgs a) {
 }
 
 hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
-    const int nzb = (a.lz + BLOCK - 1) / BLOCK;
+    const int nzb = (a.lz + ADJ_BS * ADJ_ZT - 1) / (ADJ_BS * ADJ_ZT);
     const dim3 grid((uint32_t)nzb * (uint32_t)a.lx);
     const bool f32 = (a.flags & F_ADJ_F32) != 0;
-    if (f32)
-        hipLaunchKernelGGL(adjoint_step_kernel<float>, grid, dim3(BLOCK), 0, s, a, nzb);
+    const bool m32 = (a.flags & F_MOM_F32) != 0;
+    if (f32 && m32)
+        hipLaunchKernelGGL((adjoint_step_kernel<float, float>), grid, dim3(ADJ_BS), 0, s, a, nzb);
+    else if (f32)
+        hipLaunchKernelGGL((adjoint_step_kernel<float, double>), grid, dim3(ADJ_BS), 0, s, a, nzb);
+    else if (m32)
+        hipLaunchKernelGGL((adjoint_step_kernel<double, float>), grid, dim3(ADJ_BS), 0, s, a, nzb);
     else
-        hipLaunchKernelGGL(adjoint_step_kernel<double>, grid, dim3(BLOCK), 0, s, a, nzb);
+        hipLaunchKernelGGL((adjoint_step_kernel<double, double>), grid, dim3(ADJ_BS), 0, s, a, nzb);
     if (a.flags & F_WALL_DIFFUSE) {
         const dim3 wgrid((uint32_t)((6 * a.lx + BLOCK - 1) / BLOCK));
         const bool gf = a.precision == P_F32_DEV;

@@ -32,7 +32,7 @@ int check_params(const lbm_params *p, bool *empty) {
     if (p->lx < 0 || p->lz < 0) return LBM_EINVAL;
     if ((long long)p->lx * (long long)p->lz > MAX_SITES) return LBM_EINVAL;
     if (p->precision != LBM_F64 && p->precision != LBM_F32_DEV) return LBM_EINVAL;
-    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32 | LBM_WALL_DIFFUSE))
+    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32 | LBM_WALL_DIFFUSE | LBM_MOM_F32))
         return LBM_EINVAL;
     if ((p->flags & LBM_PERIODIC_Z) && (p->flags & LBM_WALL_DIFFUSE)) return LBM_EINVAL;
     if (p->reserved != 0) return LBM_EINVAL;
@@ -55,6 +55,10 @@ size_t state_bytes(const lbm_params *p) {
 }
 size_t ghost_bytes(const lbm_params *p) { return (size_t)2 * 3 * LBM_Q * elt_size(p->precision); }
 size_t field_bytes(const lbm_params *p) { return (size_t)4 * p->lx * p->lz * sizeof(double); }
+// the step's moments output / the adjoint's moments input: double, or float with LBM_MOM_F32
+size_t mom_bytes(const lbm_params *p) {
+    return (size_t)4 * p->lx * p->lz * ((p->flags & LBM_MOM_F32) ? sizeof(float) : sizeof(double));
+}
 // diffuse-wall M/S of every ghost site for the in-place step: [2 x 3][Lx] double
 size_t wall_ratio_bytes(int lx) { return (size_t)6 * (size_t)lx * sizeof(double); }
 
@@ -189,9 +193,9 @@ int lbm_step(const lbm_params *p, const void *ghost, const void *f_in, void *f_o
     if (empty) return LBM_OK;
     const size_t sb = state_bytes(p);
     if (overlap(f_in, sb, f_out, sb) || overlap(ghost, ghost_bytes(p), f_out, sb) ||
-        overlap(moments_out, field_bytes(p), f_in, sb) ||
-        overlap(moments_out, field_bytes(p), f_out, sb) ||
-        overlap(moments_out, field_bytes(p), ghost, ghost_bytes(p)))
+        overlap(moments_out, mom_bytes(p), f_in, sb) ||
+        overlap(moments_out, mom_bytes(p), f_out, sb) ||
+        overlap(moments_out, mom_bytes(p), ghost, ghost_bytes(p)))
         return LBM_EALIAS;
     lbm::StepArgs a;
     a.f_in = f_in;
@@ -221,7 +225,7 @@ int lbm_step_inplace(const lbm_params *p, const void *ghost, void *f, int kind, 
     if (empty) return LBM_OK;
     const size_t rb = wall_ratio_bytes(p->lx);
     if (diffuse && (!scratch || scratch_bytes < rb)) return LBM_ESCRATCH;
-    const size_t sb = state_bytes(p), gb = ghost_bytes(p), fb = field_bytes(p);
+    const size_t sb = state_bytes(p), gb = ghost_bytes(p), fb = mom_bytes(p);
     if (overlap(ghost, gb, f, sb) || overlap(moments_out, fb, f, sb) || overlap(moments_out, fb, ghost, gb) ||
         (diffuse && (overlap(scratch, rb, f, sb) || overlap(scratch, rb, ghost, gb) ||
                      overlap(scratch, rb, moments_out, fb))))
@@ -356,7 +360,7 @@ int lbm_adjoint_step(const lbm_params *p, const void *ghost, const double *momen
     if (!aligned(lam_in, 16) || !aligned(lam_out, 16) || !aligned(moments, 16) || !aligned(ghost, 8))
         return LBM_EALIGN;
     if (empty) return LBM_OK;
-    const size_t lb = lam_bytes(p), mb = field_bytes(p);
+    const size_t lb = lam_bytes(p), mb = mom_bytes(p);
     if (overlap(lam_in, lb, lam_out, lb) || overlap(moments, mb, lam_out, lb) ||
         overlap(ghost, ghost_bytes(p), lam_out, lb))
         return LBM_EALIAS;

@@ -8,14 +8,14 @@
 
 namespace lbm {
 
-enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u, F_WALL_DIFFUSE = 8u };
+enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u, F_WALL_DIFFUSE = 8u, F_MOM_F32 = 16u };
 enum : int { P_F64 = 0, P_F32_DEV = 1 };
 
 struct StepArgs {
     const void *f_in;    // two-buffer step: input state (unused in place)
     void *f_out;         // two-buffer step: output state; in place: the buffer
     const void *ghost;   // [2][3][37] elements, unused with F_PERIODIC_Z
-    double *mom;         // nullable [4][lx][lz]
+    void *mom;           // nullable [4][lx][lz], double (float with F_MOM_F32)
     double *ratio;       // in place with F_WALL_DIFFUSE: scratch [2 x 3][lx]
     int lx, lz;
     double tau, omega, g;
@@ -63,7 +63,7 @@ struct InitArgs {
 hipError_t launch_init(const InitArgs &a, int precision, hipStream_t s);
 
 struct AdjointArgs {
-    const double *mom;     // [4][lx][lz] pre-collision moments of the step
+    const void *mom;       // [4][lx][lz] pre-collision moments of the step (double, or float with F_MOM_F32)
     const void *lam_in;    // [37][lx][lz] dJ/df*_t (double, or float with F_ADJ_F32)
     void *lam_out;         // [37][lx][lz] dJ/df*_{t-1}
     const void *ghost;     // [2][3][37] wall table of the forward step (F_WALL_DIFFUSE)

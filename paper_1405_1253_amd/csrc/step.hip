@@ -266,10 +266,19 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
     const double T = (e2 * inv - ux * ux - uz * uz) / D;
 
     if (a.mom && active) {
-        a.mom[site] = rho;
-        a.mom[N + site] = ux;
-        a.mom[2 * N + site] = uz;
-        a.mom[3 * N + site] = T;
+        if (a.flags & F_MOM_F32) {
+            float *m = static_cast<float *>(a.mom);
+            m[site] = (float)rho;
+            m[N + site] = (float)ux;
+            m[2 * N + site] = (float)uz;
+            m[3 * N + site] = (float)T;
+        } else {
+            double *m = static_cast<double *>(a.mom);
+            m[site] = rho;
+            m[N + site] = ux;
+            m[2 * N + site] = uz;
+            m[3 * N + site] = T;
+        }
     }
 
     // ---- force-shifted equilibrium and BGK relaxation --------------------

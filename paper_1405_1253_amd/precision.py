@@ -70,7 +70,7 @@ def gradient(steps):
     t0 = time.perf_counter()
     for prec, adj in (("f32dev", "f32"), ("f64", "f64")):
         r = Rollout(RolloutConfig.from_workload(wl, m, nsteps=steps, precision=prec, adj_precision=adj,
-                                                moment_budget_bytes=40 << 30))
+                                                mom_precision=adj, moment_budget_bytes=40 << 30))
         J = r.forward(amp)[0].item()
         grads[prec] = (J, r.backward())
         del r

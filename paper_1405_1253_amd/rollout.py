@@ -9,11 +9,15 @@ Memory schedule (two levels):
 * level 1 -- the state f*_t is checkpointed every ``ckpt_every`` steps during
   the forward pass (the initial state is checkpoint 0);
 * level 2 -- the adjoint of step t needs the 4 pre-collision moments of that
-  step.  The forward pass keeps them for the last ``keep`` steps (as many as
-  ``moment_budget_bytes`` allows); for earlier steps each checkpoint segment
-  is recomputed from its checkpoint, storing its moments, just before the
-  backward sweep crosses it.
-With every step's moments kept the backward pass needs no recomputation.
+  step (double, or float with ``mom_precision="f32"``).  The forward pass
+  keeps them for the last ``keep`` steps (as many as ``moment_budget_bytes``
+  allows); for earlier steps each checkpoint segment is recomputed from its
+  checkpoint, storing its moments, just before the backward sweep crosses it.
+  The recomputed moments go into the kept buffer, whose contents the sweep
+  has consumed by then (a separate segment buffer only when fewer than
+  ``ckpt_every`` steps are kept).
+With every step's moments kept the backward pass needs no recomputation; in
+general it recomputes nsteps - keep steps, each once.
 """
 from dataclasses import dataclass
 
@@ -44,6 +48,7 @@ class RolloutConfig:
     moment_budget_bytes: int = 64 << 30
     adj_precision: str = "f64"     # "f32": adjoint buffers in float (LBM_ADJ_F32)
     wall: str = "dirichlet"        # or "diffuse" (LBM_WALL_DIFFUSE)
+    mom_precision: str = "f64"     # "f32": stored moments in float (LBM_MOM_F32)
 
     @classmethod
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
@@ -51,6 +56,7 @@ class RolloutConfig:
         kw.setdefault("precision", wl.precision)
         kw.setdefault("adj_precision", wl.adj_precision)
         kw.setdefault("wall", wl.wall)
+        kw.setdefault("mom_precision", wl.mom_precision)
         return cls(wl.lx, wl.lz, wl.tau, wl.g, wl.t_d, wl.t_m, wl.t_u, wl.width, modes.k,
                    modes.phase, wl.steps if nsteps is None else nsteps, **kw)
 
@@ -64,6 +70,7 @@ class Rollout:
         self.params = abi.make_params(c.lx, c.lz, c.tau, c.g,
                                       abi.F64 if c.precision == "f64" else abi.F32_DEV,
                                       (abi.ADJ_F32 if c.adj_precision == "f32" else 0)
+                                      | (abi.MOM_F32 if c.mom_precision == "f32" else 0)
                                       | abi.wall_flag(c.wall))
         self.ldtype = torch.float32 if c.adj_precision == "f32" else torch.float64
         self.desc = abi.RT3Desc(c.t_d, c.t_m, c.t_u, c.width, c.k, c.phase)
@@ -73,12 +80,17 @@ class Rollout:
         self.ghost = torch.empty((2, 3, abi.Q), dtype=self.sdtype, device=self.device)
         self.scratch = torch.empty(max(abi.lbm_scratch_bytes(self.params), 256), dtype=torch.uint8,
                                    device=self.device)
-        mbytes = 4 * c.lx * c.lz * 8
+        mdtype = torch.float32 if c.mom_precision == "f32" else torch.float64
+        mbytes = 4 * c.lx * c.lz * (4 if c.mom_precision == "f32" else 8)
         self.keep = int(min(c.nsteps, c.moment_budget_bytes // mbytes))
         self.first_kept = c.nsteps - self.keep + 1          # steps >= this keep their moments
-        self.kept = torch.empty((self.keep, 4, c.lx, c.lz), dtype=torch.float64, device=self.device)
-        seg = 0 if self.keep >= c.nsteps else c.ckpt_every
-        self.segbuf = torch.empty((seg, 4, c.lx, c.lz), dtype=torch.float64, device=self.device)
+        self.kept = torch.empty((self.keep, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
+        if self.keep >= c.nsteps:
+            self.segbuf = self.kept[:0]
+        elif self.keep >= c.ckpt_every:
+            self.segbuf = self.kept[:c.ckpt_every]          # reused once the sweep has passed it
+        else:
+            self.segbuf = torch.empty((c.ckpt_every, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
         self.ckpt = {}
         self.recomputed_steps = 0
 

@@ -50,6 +50,7 @@ class Workload:
                               # (the single-front run's "virtual" T_m)
     wall: str = "dirichlet"   # wall rule: "dirichlet" or "diffuse" (mass-conserving)
     inplace: bool = False     # single population buffer (lbm_step_inplace)
+    mom_precision: str = "f64"  # adjoint workloads: "f32" = stored moments in float
 
     @property
     def g(self) -> float:
@@ -77,7 +78,7 @@ WORKLOADS = {
         Workload("rt3_4096x12288_inplace", 4096, 12288, 1000, "f64", 1405, inplace=True),
         Workload("rt3_4096x12288_f32_inplace", 4096, 12288, 20000, "f32dev", 1405, inplace=True),
         Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250,
-                 adj_precision="f32"),
+                 adj_precision="f32", mom_precision="f32"),
         # The runs of Sec. IV, Table II: 2400 x 6144, g = 1.5e-5, T 1.025/1/0.975,
         # a middle layer delta = 500 for the double front; Ra = 1e10 at Pr = 1
         # gives nu = sqrt(dT Lz^3 g / Ra) = 5.46e-3 with Lz in length units.

@@ -65,7 +65,7 @@ def test_step_rejects_bad_arguments(abi):
     assert _call_step(abi, mk(-1, 16, 0.7, 0.0)) == -1
     assert _call_step(abi, mk(1 << 15, 1 << 15, 0.7, 0.0)) == -1  # too many sites
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, precision=7)) == -1
-    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=16)) == -1          # unknown flag
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=32)) == -1          # unknown flag
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=abi.PERIODIC_Z | abi.WALL_DIFFUSE)) == -1
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=abi.WALL_DIFFUSE), ghost=None) == -1
     p = mk(16, 16, 0.7, 0.0)

@@ -203,3 +203,48 @@ def test_gradient_float_storage_and_adjoint_vs_f64(abi):
         print(f"state {key[0]}, adjoint {key[1]}: J rel err {abs(J / J64 - 1):.2e}, "
               f"grad max err / max|grad| {err:.2e}")
         assert err <= 1e-3
+
+
+def test_float_moments(abi):
+    """LBM_MOM_F32: lbm_step writes the moments rounded to float (bit for bit
+    the double moments' rounding); the adjoint step reading them differs from
+    the one reading double moments by the effect of that rounding, bounded
+    here by 1e-6 of the largest entry (the float rounding is 6e-8 relative)."""
+    lx, lz = 128, 384
+    p, f, ghost = _state(lx, lz, 0.7, 2e-3, 21)
+    lam = np.random.default_rng(22).standard_normal((37, lx, lz))
+    fin, gh = _t(f), _t(ghost)
+    fout = torch.empty_like(fin)
+    m64 = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
+    m32 = torch.empty((4, lx, lz), dtype=torch.float32, device=DEV)
+    p64 = abi.make_params(lx, lz, p.tau, p.g)
+    p32 = abi.make_params(lx, lz, p.tau, p.g, flags=abi.MOM_F32)
+    abi.lbm_step(p64, gh, fin, fout, m64)
+    abi.lbm_step(p32, gh, fin, fout, m32)
+    assert torch.equal(m32, m64.float())
+    out64 = torch.empty_like(fin)
+    out32 = torch.empty_like(fin)
+    abi.lbm_adjoint_step(p64, gh, m64, _t(lam), out64)
+    abi.lbm_adjoint_step(p32, gh, m32, _t(lam), out32)
+    err = _rel_max(out32.cpu().numpy(), out64.cpu().numpy())
+    print(f"adjoint step with float moments: {err:.2e} of max")
+    assert err <= 1e-6
+
+
+def test_rollout_float_moments_vs_oracle(abi):
+    """20-step gradient at 128 x 384 with float moments (and the segment
+    buffer inside the kept buffer: keep 10, checkpoints every 5) against the
+    oracle adjoint: 1e-5 of the largest entry."""
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    n = 20
+    _, g_o = A.rollout_gradient(O.Params(wl.lx, wl.lz, wl.tau, wl.g),
+                                O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase), m.amp, n)
+    r = _rollout(wl, m, n, mom_precision="f32", ckpt_every=5, moment_budget_bytes=10 * 4 * wl.lx * wl.lz * 4)
+    assert r.keep == 10 and r.segbuf.data_ptr() == r.kept.data_ptr()
+    r.forward(torch.as_tensor(m.amp, device=DEV))
+    got = r.backward().cpu().numpy()
+    err = _rel_max(got, g_o)
+    print(f"float moments: gradient {err:.2e} of max; recomputed {r.recomputed_steps}")
+    assert r.recomputed_steps == 10
+    assert err <= 1e-5
