@@ -102,15 +102,15 @@ def cpu_baseline(wl, columns=32, min_seconds=10.0, max_steps=64):
 def adjoint_ratio(name, budget_bytes=None, warm=True):
     """Wall time of the rollout's forward pass (with checkpoints and stored
     moments) and of its backward pass (recomputation + adjoint sweep + init
-    VJP), against a plain forward of the same steps: the plain forward is
-    timed twice after a warm-up (the mean is the reference), the rollout once
-    (after one warm-up run of every phase if ``warm``).  Also the adjoint step
-    alone (20 launches on the rollout's buffers, HIP events) with its HBM
-    bandwidth at 37 x 2 adjoint elements + 4 moments per site."""
+    VJP), against a plain forward of the same steps on the rollout's own
+    state buffers (so that both run on the same memory): the plain forward
+    is timed twice after a warm-up (the mean is the reference), the rollout
+    once (after one warm-up run of every phase if ``warm``).  Also the
+    adjoint step alone (20 launches on the rollout's buffers, HIP events)
+    with its HBM bandwidth at 37 x 2 adjoint elements + 4 moments per site."""
     import torch
     from paper_1405_1253_amd import abi
     from paper_1405_1253_amd.rollout import Rollout, RolloutConfig
-    from paper_1405_1253_amd.runtime import Lattice
     from paper_1405_1253_amd.workload import WORKLOADS, draw_modes
     wl = WORKLOADS[name]
     m = draw_modes(wl.seed)
@@ -124,11 +124,6 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
 
-    lat = Lattice.from_workload(wl, modes=m)
-    lat.step(wl.steps if warm else 200)                 # warm-up
-    t_plain = [timed(lambda: lat.step(wl.steps))[0] for _ in range(2)]
-    del lat
-    torch.cuda.empty_cache()
     r = Rollout(RolloutConfig.from_workload(wl, m, **kw))
     if warm:
         r.forward(amp)
@@ -136,6 +131,17 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
     r.recomputed_steps = 0
     t_fwd, _ = timed(lambda: r.forward(amp))
     t_bwd, grad = timed(r.backward)
+
+    def plain_forward(n):
+        for i in range(n):
+            abi.lbm_step(r.params, r.ghost, r.buf[i % 2], r.buf[1 - i % 2])
+
+    abi.lbm_init_rt3(r.params, r.desc, r.amp, r.buf[0], r.ghost)
+    plain_forward(wl.steps if warm else 200)             # warm-up
+    t_plain = []
+    for _ in range(2):
+        abi.lbm_init_rt3(r.params, r.desc, r.amp, r.buf[0], r.ghost)
+        t_plain.append(timed(lambda: plain_forward(wl.steps))[0])
     plain = sum(t_plain) / len(t_plain)
 
     # the adjoint step alone, on the rollout's buffers
