@@ -262,7 +262,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = [adjoint_ratio("rt3_512x1536_adj"),
                           adjoint_ratio("rt3_512x1536_adj_diffuse"),
-                          adjoint_ratio("rt3_2048x6144_adj", 212 << 30, warm=False)]
+                          adjoint_ratio("rt3_2048x6144_adj", 232 << 30, warm=False)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -7,7 +7,9 @@ lbm_init_rt3_vjp); this module only schedules them and manages memory.
 
 Memory schedule (two levels):
 * level 1 -- the state f*_t is checkpointed every ``ckpt_every`` steps during
-  the forward pass (the initial state is checkpoint 0);
+  the forward pass (the initial state is checkpoint 0); ``ckpt_every = 0``
+  sets the interval to the number of kept steps, the largest segment the
+  kept buffer can hold, which needs the fewest checkpoints;
 * level 2 -- the adjoint of step t needs the 4 pre-collision moments of that
   step (double, or float with ``mom_precision="f32"``).  The forward pass
   keeps them for the last ``keep`` steps (as many as ``moment_budget_bytes``
@@ -52,7 +54,7 @@ class RolloutConfig:
 
     @classmethod
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
-        kw.setdefault("ckpt_every", wl.ckpt_every or 100)
+        kw.setdefault("ckpt_every", wl.ckpt_every)
         kw.setdefault("precision", wl.precision)
         kw.setdefault("adj_precision", wl.adj_precision)
         kw.setdefault("wall", wl.wall)
@@ -85,12 +87,13 @@ class Rollout:
         self.keep = int(min(c.nsteps, c.moment_budget_bytes // mbytes))
         self.first_kept = c.nsteps - self.keep + 1          # steps >= this keep their moments
         self.kept = torch.empty((self.keep, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
+        self.ckpt_every = c.ckpt_every if c.ckpt_every > 0 else (self.keep if self.keep > 0 else 100)
         if self.keep >= c.nsteps:
             self.segbuf = self.kept[:0]
-        elif self.keep >= c.ckpt_every:
-            self.segbuf = self.kept[:c.ckpt_every]          # reused once the sweep has passed it
+        elif self.keep >= self.ckpt_every:
+            self.segbuf = self.kept[:self.ckpt_every]       # reused once the sweep has passed it
         else:
-            self.segbuf = torch.empty((c.ckpt_every, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
+            self.segbuf = torch.empty((self.ckpt_every, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
         self.ckpt = {}
         self.recomputed_steps = 0
 
@@ -110,7 +113,7 @@ class Rollout:
         for t in range(1, c.nsteps + 1):
             self._step(self.buf[cur], self.buf[1 - cur], self._mom_slot(t))
             cur = 1 - cur
-            if t % c.ckpt_every == 0 and t < c.nsteps and t < self.first_kept:
+            if t % self.ckpt_every == 0 and t < c.nsteps and t < self.first_kept:
                 self.ckpt[t] = self.buf[cur].clone()
         self.final = self.buf[cur]
         self.j = torch.empty(3, dtype=torch.float64, device=self.device)
@@ -134,7 +137,7 @@ class Rollout:
                 t -= 1
                 continue
             # recompute the checkpoint segment (a, b] that contains t
-            a = ((t - 1) // c.ckpt_every) * c.ckpt_every
+            a = ((t - 1) // self.ckpt_every) * self.ckpt_every
             b = t
             self.buf[0].copy_(self.ckpt[a])
             cur = 0

@@ -41,7 +41,8 @@ class Workload:
     t_m: float = 1.00
     t_u: float = 0.95
     width: float = 4.0
-    ckpt_every: int = 0       # adjoint workloads: state checkpoint interval
+    ckpt_every: int = 0       # adjoint workloads: state checkpoint interval (0: as many
+                              # steps as the kept moments cover)
     adj_precision: str = "f64"  # adjoint workloads: "f32" = float adjoint buffers
     z_lo: float = None        # interface rest heights (sites); None: Lz/3, 2 Lz/3
     z_hi: float = None
@@ -77,7 +78,7 @@ WORKLOADS = {
                  wall="diffuse"),
         Workload("rt3_4096x12288_inplace", 4096, 12288, 1000, "f64", 1405, inplace=True),
         Workload("rt3_4096x12288_f32_inplace", 4096, 12288, 20000, "f32dev", 1405, inplace=True),
-        Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=250,
+        Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=0,
                  adj_precision="f32", mom_precision="f32"),
         # The runs of Sec. IV, Table II: 2400 x 6144, g = 1.5e-5, T 1.025/1/0.975,
         # a middle layer delta = 500 for the double front; Ra = 1e10 at Pr = 1

@@ -248,3 +248,8 @@ def test_rollout_float_moments_vs_oracle(abi):
     print(f"float moments: gradient {err:.2e} of max; recomputed {r.recomputed_steps}")
     assert r.recomputed_steps == 10
     assert err <= 1e-5
+    # checkpoint interval = kept steps (ckpt_every = 0): the same gradient
+    r0 = _rollout(wl, m, n, mom_precision="f32", ckpt_every=0, moment_budget_bytes=10 * 4 * wl.lx * wl.lz * 4)
+    assert r0.ckpt_every == 10
+    r0.forward(torch.as_tensor(m.amp, device=DEV))
+    assert np.array_equal(r0.backward().cpu().numpy(), got)
