@@ -63,6 +63,34 @@ class RolloutConfig:
                    modes.phase, wl.steps if nsteps is None else nsteps, **kw)
 
 
+def checkpoint_steps(nsteps, keep, ckpt_every):
+    """Steps after which the forward pass stores the state (0 = the initial
+    state): every ``ckpt_every`` steps, up to the first step whose moments
+    are kept."""
+    first_kept = nsteps - keep + 1
+    return [0] + [t for t in range(ckpt_every, nsteps, ckpt_every) if t < first_kept]
+
+
+def backward_plan(nsteps, keep, ckpt_every):
+    """The backward sweep as a list of operations, in order:
+    ("adjoint", t, "kept", i)   adjoint of step t with the moments in kept[i];
+    ("recompute", a, b)         restore checkpoint a, recompute steps a+1..b,
+                                moments of step s into segment slot s-a-1;
+    ("adjoint", t, "seg", i)    adjoint of step t with segment slot i."""
+    first_kept = nsteps - keep + 1
+    plan, t = [], nsteps
+    while t >= 1:
+        if t >= first_kept:
+            plan.append(("adjoint", t, "kept", t - first_kept))
+            t -= 1
+            continue
+        a = ((t - 1) // ckpt_every) * ckpt_every     # the checkpoint segment (a, t]
+        plan.append(("recompute", a, t))
+        plan.extend(("adjoint", s, "seg", s - a - 1) for s in range(t, a, -1))
+        t = a
+    return plan
+
+
 class Rollout:
     """Forward/backward driver with checkpointing (one GPU)."""
 
@@ -110,10 +138,11 @@ class Rollout:
         abi.lbm_init_rt3(self.params, self.desc, self.amp, self.buf[0], self.ghost)
         cur = 0
         self.ckpt = {0: self.buf[0].clone()}
+        saves = set(checkpoint_steps(c.nsteps, self.keep, self.ckpt_every))
         for t in range(1, c.nsteps + 1):
             self._step(self.buf[cur], self.buf[1 - cur], self._mom_slot(t))
             cur = 1 - cur
-            if t % self.ckpt_every == 0 and t < c.nsteps and t < self.first_kept:
+            if t in saves:
                 self.ckpt[t] = self.buf[cur].clone()
         self.final = self.buf[cur]
         self.j = torch.empty(3, dtype=torch.float64, device=self.device)
@@ -128,28 +157,20 @@ class Rollout:
         """dJ/d amp [2, nmodes] (device float64)."""
         c = self.cfg
         li = 0
-        t = c.nsteps
-        while t >= 1:
-            if t >= self.first_kept:
-                abi.lbm_adjoint_step(self.params, self.ghost, self.kept[t - self.first_kept], self.lam[li],
-                                     self.lam[1 - li])
-                li = 1 - li
-                t -= 1
+        for op in backward_plan(c.nsteps, self.keep, self.ckpt_every):
+            if op[0] == "recompute":
+                _, a, b = op
+                self.buf[0].copy_(self.ckpt[a])
+                cur = 0
+                for s in range(a + 1, b + 1):
+                    self._step(self.buf[cur], self.buf[1 - cur], self.segbuf[s - a - 1])
+                    cur = 1 - cur
+                self.recomputed_steps += b - a
                 continue
-            # recompute the checkpoint segment (a, b] that contains t
-            a = ((t - 1) // self.ckpt_every) * self.ckpt_every
-            b = t
-            self.buf[0].copy_(self.ckpt[a])
-            cur = 0
-            for s in range(a + 1, b + 1):
-                self._step(self.buf[cur], self.buf[1 - cur], self.segbuf[s - a - 1])
-                cur = 1 - cur
-            self.recomputed_steps += b - a
-            for s in range(b, a, -1):
-                abi.lbm_adjoint_step(self.params, self.ghost, self.segbuf[s - a - 1], self.lam[li],
-                                     self.lam[1 - li])
-                li = 1 - li
-            t = a
+            _, t, where, i = op
+            mom = self.kept[i] if where == "kept" else self.segbuf[i]
+            abi.lbm_adjoint_step(self.params, self.ghost, mom, self.lam[li], self.lam[1 - li])
+            li = 1 - li
         d_amp = torch.empty_like(self.amp)
         abi.lbm_init_rt3_vjp(self.params, self.desc, self.amp, self.lam[li], d_amp, self.scratch)
         return d_amp
