@@ -202,7 +202,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU x-slab "
-              "decomposition is not part of this build.", file=sys.stderr)
+              "decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
