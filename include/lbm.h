@@ -63,7 +63,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2u
+#define LBM_ABI_VERSION 3u
 #define LBM_Q 37
 #define LBM_MAX_MODES 32 /* interface modes per front accepted by lbm_init_rt3 */
 
@@ -268,7 +268,7 @@ int lbm_profiles(const lbm_params *params, const void *f, double *prof, void *sc
  *
  *   desc      (host) only t_d > t_m > t_u are used
  *   f         (device) state buffer
- *   j_out     (device) double [3]: J, KE, L_u + L_d
+ *   j_out     (device) double [5]: J, KE, L_u + L_d, L_u, L_d
  *   lam_seed  (device, nullable) [37][Lx][Lz] (double, or float with LBM_ADJ_F32):
  *             dJ/df_l at every site
  *             (the tent map's slope is taken as 2, -2, 0 on the three pieces)

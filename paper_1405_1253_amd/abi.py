@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 Q = 37
 MAX_MODES = 32
 F64, F32_DEV = 0, 1
@@ -196,7 +196,8 @@ def _nbytes(t):
 
 
 def lbm_objective(params, desc, f, wk, wl, j_out, lam_seed=None, scratch=None, stream=None):
-    """J = wk KE + wl (L_u + L_d) into j_out[3] and optionally dJ/df (see include/lbm.h)."""
+    """J = wk KE + wl (L_u + L_d) into j_out[5] = (J, KE, L_u + L_d, L_u, L_d) and
+    optionally dJ/df (see include/lbm.h)."""
     st = load().lbm_objective(ctypes.byref(params), ctypes.byref(desc.c), _ptr(f), wk, wl,
                               _ptr(j_out), _ptr(lam_seed), _ptr(scratch), _nbytes(scratch),
                               _stream(stream))

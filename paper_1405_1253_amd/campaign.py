@@ -37,7 +37,7 @@ def run(wl, nsteps, every, profile_times=(), progress=None):
     from . import abi
     from .runtime import Lattice
     lat = Lattice.from_workload(wl)
-    t_rec, L_rec, ke_rec, prof = [], [], [], {}
+    t_rec, L_rec, Lu_rec, Ld_rec, ke_rec, prof = [], [], [], [], [], {}
     want = sorted(set(int(x) for x in profile_times))
     t = 0
     t0 = time.perf_counter()
@@ -47,6 +47,8 @@ def run(wl, nsteps, every, profile_times=(), progress=None):
             t_rec.append(t)
             ke_rec.append(j[1])
             L_rec.append(j[2])
+            Lu_rec.append(j[3])
+            Ld_rec.append(j[4])
             if not np.isfinite(j).all():
                 raise FloatingPointError(f"state diverged at step {t}")
         if t in want:
@@ -63,7 +65,8 @@ def run(wl, nsteps, every, profile_times=(), progress=None):
             progress(t, L_rec[-1], time.perf_counter() - t0)
     torch.cuda.synchronize()
     r = abi.lbm_lattice()[0]
-    return {"t": np.array(t_rec), "L_tot": np.array(L_rec), "KE": np.array(ke_rec),
+    return {"t": np.array(t_rec), "L_tot": np.array(L_rec), "L_u": np.array(Lu_rec),
+            "L_d": np.array(Ld_rec), "KE": np.array(ke_rec),
             "profile_steps": np.array(sorted(prof)),
             "profiles": np.array([prof[k] for k in sorted(prof)]),
             "tau_rt": rt_time(wl, r), "atwood": wl.atwood, "g": wl.g,

@@ -417,6 +417,8 @@ __global__ __launch_bounds__(BLOCK) void objective_pass2(ObjectiveArgs a, ObjLay
         a.j_out[0] = a.wk * red[2][0] + a.wl * L_;
         a.j_out[1] = red[2][0];
         a.j_out[2] = L_;
+        a.j_out[3] = red[0][0];
+        a.j_out[4] = red[1][0];
     }
 }
 

@@ -329,8 +329,8 @@ int lbm_objective(const lbm_params *p, const lbm_rt3_desc *d, const void *f, dou
     const size_t need = lbm::objective_scratch_bytes(p->lx, p->lz);
     if (!scratch || scratch_bytes < need) return LBM_ESCRATCH;
     const size_t sb = state_bytes(p), lb = lam_bytes(p);
-    if (overlap(j_out, 24, f, sb) || overlap(lam_seed, lb, f, sb) || overlap(scratch, need, f, sb) ||
-        overlap(j_out, 24, lam_seed, lb) || overlap(j_out, 24, scratch, need) ||
+    if (overlap(j_out, 40, f, sb) || overlap(lam_seed, lb, f, sb) || overlap(scratch, need, f, sb) ||
+        overlap(j_out, 40, lam_seed, lb) || overlap(j_out, 40, scratch, need) ||
         overlap(lam_seed, lb, scratch, need))
         return LBM_EALIAS;
     lbm::ObjectiveArgs a;

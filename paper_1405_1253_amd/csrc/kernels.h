@@ -77,7 +77,7 @@ hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s);
 struct ObjectiveArgs {
     const void *f;
     void *scratch;
-    double *j_out;         // [3]: J, KE, L_u + L_d
+    double *j_out;         // [5]: J, KE, L_u + L_d, L_u, L_d
     void *lam_seed;        // nullable [37][lx][lz], double or float
     int lx, lz;
     bool lam_f32;

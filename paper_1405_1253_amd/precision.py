@@ -7,7 +7,8 @@ fields:   the 4096 x 12288 three-layer workload is run in FP64 and in FP32
           deviation storage for the same number of steps; the renormalised
           fields (rho, u^H_x, u^H_z, T^H) are compared site by site (max and
           RMS absolute error per field, and the max relative error of rho and
-          T) and the mixing lengths L_u + L_d and KE of both runs are printed.
+          T) and the mixing lengths of both fronts (L_u, L_d, their sum) and
+          KE of both runs are printed.
 gradient: dJ/d amp of the 2048 x 6144 rollout with FP32 storage and float
           adjoint buffers against the same rollout in FP64 throughout.
 Each mode prints one JSON line.  All arithmetic runs in the library's kernels;
@@ -55,6 +56,8 @@ def fields(steps):
     j64 = lat64.objective().cpu().tolist()
     j32 = lat32.objective().cpu().tolist()
     res["mixing_length_f64"], res["mixing_length_f32"] = j64[2], j32[2]
+    res["L_u_f64"], res["L_u_f32"] = j64[3], j32[3]
+    res["L_d_f64"], res["L_d_f32"] = j64[4], j32[4]
     res["ke_f64"], res["ke_f32"] = j64[1], j32[1]
     res["seconds"] = time.perf_counter() - t0
     return res

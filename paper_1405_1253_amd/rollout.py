@@ -145,7 +145,7 @@ class Rollout:
             if t in saves:
                 self.ckpt[t] = self.buf[cur].clone()
         self.final = self.buf[cur]
-        self.j = torch.empty(3, dtype=torch.float64, device=self.device)
+        self.j = torch.empty(5, dtype=torch.float64, device=self.device)
         self.lam = [torch.empty((abi.Q, c.lx, c.lz), dtype=self.ldtype, device=self.device)
                     for _ in range(2)]
         abi.lbm_objective(self.params, self.desc, self.final, c.wk, c.wl, self.j, self.lam[0],

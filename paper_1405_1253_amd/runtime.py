@@ -100,8 +100,8 @@ class Lattice:
         return out
 
     def objective(self, wk=1.0, wl=1.0):
-        """[3]: J = wk KE + wl (L_u + L_d), KE, L_u + L_d of the current state."""
-        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        """[5]: J = wk KE + wl (L_u + L_d), KE, L_u + L_d, L_u, L_d of the current state."""
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
         abi.lbm_objective(self.params, self.diag_desc, self.state, wk, wl, out, None, self.scratch)
         return out
 

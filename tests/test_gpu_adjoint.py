@@ -68,7 +68,7 @@ def test_objective_and_seed_parity(abi):
     p, f, _ = _state(lx, lz, 0.7, 1e-3, 3, steps=5)
     desc = abi.RT3Desc(1.05, 1.0, 0.95, 3.0)
     params = abi.make_params(lx, lz, p.tau, p.g)
-    j = torch.empty(3, dtype=torch.float64, device=DEV)
+    j = torch.empty(5, dtype=torch.float64, device=DEV)
     seed = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
     scratch = torch.empty(abi.lbm_scratch_bytes(params), dtype=torch.uint8, device=DEV)
     abi.lbm_objective(params, desc, _t(f), 2.0, 0.5, j, seed, scratch)
@@ -76,6 +76,9 @@ def test_objective_and_seed_parity(abi):
     got = j.cpu().numpy()
     assert L > 1.0 and ke > 0.0
     assert abs(got[0] / Jo - 1) <= 1e-12 and abs(got[1] / ke - 1) <= 1e-12 and abs(got[2] / L - 1) <= 1e-12
+    Lu, Ld = O.mixing_lengths(O.tbar(O.hydro_fields(f, p)[2]), 0.95, 1.0, 1.05)
+    assert Lu > 0.5 and Ld > 0.5
+    assert abs(got[3] / Lu - 1) <= 1e-12 and abs(got[4] / Ld - 1) <= 1e-12
     want = A.objective_vjp(f, p, 0.95, 1.0, 1.05, 2.0, 0.5)
     assert _rel_max(seed.cpu().numpy(), want) <= 1e-12
 
