@@ -78,6 +78,9 @@ WORKLOADS = {
                  wall="diffuse"),
         Workload("rt3_4096x12288_inplace", 4096, 12288, 1000, "f64", 1405, inplace=True),
         Workload("rt3_4096x12288_f32_inplace", 4096, 12288, 20000, "f32dev", 1405, inplace=True),
+        # the largest lattice the library accepts (2^29 sites): one FP64
+        # buffer of 159 GB; two would not fit in one GPU's 288 GB
+        Workload("rt3_16384x32768_inplace", 16384, 32768, 1000, "f64", 1405, inplace=True),
         Workload("rt3_2048x6144_adj", 2048, 6144, 5000, "f32dev", 1405, ckpt_every=0,
                  adj_precision="f32", mom_precision="f32"),
         # The runs of Sec. IV, Table II: 2400 x 6144, g = 1.5e-5, T 1.025/1/0.975,

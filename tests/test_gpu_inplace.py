@@ -162,3 +162,56 @@ def test_lattice_in_place_runtime(abi):
     assert float(((lat.state - ref.state).abs() / ref.state.abs()).max()) <= 1e-13
     a, b = lat.sums(), ref.sums()              # mass, momentum (~0 in x), energy
     assert float((a - b).abs().max()) <= 1e-12 * float(b[0])
+
+
+def _oracle_column(wl, m, x, nsteps):
+    # a site after n steps depends on columns within 3n of it (Dirichlet
+    # walls): step a periodic window of 6n + 1 columns around x
+    half = 3 * nsteps
+    cols = (np.arange(x - half, x + half + 1)) % wl.lx
+    desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
+    f, ghost = O.init_rt3(O.Params(wl.lx, wl.lz, wl.tau, wl.g), desc, m.amp, columns=cols)
+    return O.run(f, ghost, O.Params(len(cols), wl.lz, wl.tau, wl.g), nsteps)[:, half, :]
+
+
+def test_largest_lattice_single_buffer(abi):
+    """16384 x 32768 = 2^29 sites, the largest lattice the library accepts, in
+    FP64 on one 159 GB buffer (two buffers would need 318 GB): sampled
+    columns, both wrap-around edges among them, against the oracle's windowed
+    columns after the initial state and after 2 steps (1e-12 relative), and
+    the mass lbm_moments reports against a plain sum of the buffer; the rate
+    of 10 more steps is printed."""
+    from paper_1405_1253_amd.runtime import Lattice
+    wl = W.WORKLOADS["rt3_16384x32768_inplace"]
+    assert wl.sites == 1 << 29
+    torch.cuda.empty_cache()
+    need = 37 * 8 * wl.sites
+    free = torch.cuda.mem_get_info()[0]
+    if free < need + (8 << 30):
+        pytest.skip(f"needs {need / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
+    m = W.draw_modes(wl.seed)
+    lat = Lattice.from_workload(wl, modes=m)
+    assert lat.inplace and len(lat.buf) == 1
+    samples = (0, 8191, 16383)
+    got = {0: {x: lat.state[:, x, :].cpu().numpy() for x in samples}}
+    lat.step(2)
+    got[2] = {x: lat.state[:, x, :].cpu().numpy() for x in samples}
+    mass, total = lat.sums()[0].item(), lat.state.sum().item()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    lat.step(10)
+    stop.record()
+    stop.synchronize()
+    ms = start.elapsed_time(stop) / 10
+    del lat
+    torch.cuda.empty_cache()
+    worst = {}
+    for n, cols in got.items():
+        for x, g in cols.items():
+            want = _oracle_column(wl, m, x, n)
+            worst[n] = max(worst.get(n, 0.0), float(np.max(np.abs(g - want) / want)))
+    gbs = 2 * need / (ms * 1e-3) / 1e9
+    print(f"2^29 sites, one FP64 buffer: max rel err init {worst[0]:.2e}, 2 steps {worst[2]:.2e}; "
+          f"lbm_moments mass vs a plain sum {abs(mass / total - 1):.1e}; {ms:.1f} ms/step, {gbs:.0f} GB/s")
+    assert worst[0] <= 1e-12 and worst[2] <= 1e-12
+    assert abs(mass / total - 1) <= 1e-12
