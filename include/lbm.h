@@ -85,7 +85,8 @@ enum lbm_flags {
     LBM_PERIODIC_Z = 1u, /* test mode: z wraps like x, no walls, ghost unused           */
     LBM_NO_COLLIDE = 2u, /* test mode: streaming and walls only                          */
     LBM_ADJ_F32 = 4u,    /* adjoint buffers (lam_seed, lam_in/lam_out, lam0) are float,
-                            not double; the adjoint arithmetic stays double            */
+                            not double; the adjoint arithmetic stays double, except
+                            in lbm_adjoint_step with LBM_MOM_F32 as well            */
     LBM_WALL_DIFFUSE = 8u, /* mass-conserving diffuse walls instead of Dirichlet walls
                             (lbm_step); not with LBM_PERIODIC_Z                       */
     LBM_MOM_F32 = 16u     /* the step's moments_out and the adjoint's moments are float
@@ -303,8 +304,12 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  *   lam_in   (device) [37][Lx][Lz], double (float with LBM_ADJ_F32)
  *   lam_out  (device) same type and shape, must not overlap lam_in, moments
  *            or ghost
- * The adjoint arithmetic is double; params->precision names the forward
- * state it belongs to and the element type of ghost.
+ * The adjoint arithmetic is double, except with both LBM_ADJ_F32 and
+ * LBM_MOM_F32 (all inputs float): then the per-site sums of lam_in against
+ * the 15 monomials xi_x^p xi_z^q (p + q <= 4) and the outputs G_l are formed
+ * in float, and the moments' algebra and (alpha, beta, gamma) in double
+ * (error about 10 float roundings of the largest output).  params->precision
+ * names the forward state it belongs to and the element type of ghost.
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
  */
 int lbm_adjoint_step(const lbm_params *params, const void *ghost, const double *moments,

@@ -57,42 +57,59 @@ namespace lbm {
 //   sum dP/dth   = (u2 + 2 th - 1) M_1 + (1/2 - u2/4 - 2 th) M_xi2 + th/4 M_xi2^2
 //                  + M_xi2x/2 - 2 M_x + M_xi2x^2/4 - 3/2 M_x^2.
 // The moments are a constant linear map of the 37 inputs (15 accumulators),
-// which keeps the register footprint small.
+// which keeps the register footprint small.  In the all-float mode (float
+// adjoint buffers and float stored moments) the 15 sums and the outputs G
+// are formed in float: about 40 % fewer operations than in double, and the
+// inputs already carry float rounding.
 struct EqVjp {
     double sp, sxx, sxz, su2, sth;
 };
 
-template <typename LT>
+// The +-e pairs (l, l + 1) share their weight and have opposite velocities,
+// so a monomial of even degree sees lam_l + lam_{l+1} and one of odd degree
+// lam_l - lam_{l+1}: 18 pairs instead of 37 terms per sum.
+__host__ __device__ constexpr bool pairs_share_weight() {
+    for (int l = 1; l < Q; l += 2)
+        if (W[l] != W[l + 1] || EX[l + 1] != -EX[l] || EZ[l + 1] != -EZ[l]) return false;
+    return true;
+}
+static_assert(pairs_share_weight(), "population l + 1 must be -e_l with the weight of l, l odd");
+
+// A: accumulator type of the 15 sums (double; float in the all-float mode)
+template <typename A, typename LT>
 __device__ __forceinline__ EqVjp eq_vjp_sums(const LT lam[Q], double vx, double vz, double th) {
-    // m[p][q]: p powers of xi_x, q of xi_z
-    double m00 = 0, m10 = 0, m01 = 0, m20 = 0, m11 = 0, m02 = 0, m30 = 0, m21 = 0, m12 = 0, m03 = 0;
-    double m40 = 0, m31 = 0, m22 = 0, m13 = 0, m04 = 0;
+    // q[p][q]: p powers of xi_x, q of xi_z
+    A q00 = (A)lam[0] * (A)W[0], q10 = 0, q01 = 0, q20 = 0, q11 = 0, q02 = 0, q30 = 0, q21 = 0, q12 = 0,
+      q03 = 0, q40 = 0, q31 = 0, q22 = 0, q13 = 0, q04 = 0;
 #pragma unroll
-    for (int l = 0; l < Q; ++l) {
-        const double lw = (double)lam[l] * W[l];
+    for (int l = 1; l < Q; l += 2) {
+        const A s = ((A)lam[l] + (A)lam[l + 1]) * (A)W[l];   // even degrees
+        const A d = ((A)lam[l] - (A)lam[l + 1]) * (A)W[l];   // odd degrees
         const double a = R * EX[l], b = R * EZ[l];
-        m00 += lw;
+        q00 += s;
         if (EX[l] != 0) {
-            m10 += lw * a;
-            m20 += lw * (a * a);
-            m30 += lw * (a * a * a);
-            m40 += lw * (a * a * a * a);
+            q10 += d * (A)a;
+            q20 += s * (A)(a * a);
+            q30 += d * (A)(a * a * a);
+            q40 += s * (A)(a * a * a * a);
         }
         if (EZ[l] != 0) {
-            m01 += lw * b;
-            m02 += lw * (b * b);
-            m03 += lw * (b * b * b);
-            m04 += lw * (b * b * b * b);
+            q01 += d * (A)b;
+            q02 += s * (A)(b * b);
+            q03 += d * (A)(b * b * b);
+            q04 += s * (A)(b * b * b * b);
         }
         if (EX[l] != 0 && EZ[l] != 0) {
-            m11 += lw * (a * b);
-            m21 += lw * (a * a * b);
-            m12 += lw * (a * b * b);
-            m31 += lw * (a * a * a * b);
-            m22 += lw * (a * a * b * b);
-            m13 += lw * (a * b * b * b);
+            q11 += s * (A)(a * b);
+            q21 += d * (A)(a * a * b);
+            q12 += d * (A)(a * b * b);
+            q31 += s * (A)(a * a * a * b);
+            q22 += s * (A)(a * a * b * b);
+            q13 += s * (A)(a * b * b * b);
         }
     }
+    const double m00 = q00, m10 = q10, m01 = q01, m20 = q20, m11 = q11, m02 = q02, m30 = q30, m21 = q21,
+                 m12 = q12, m03 = q03, m40 = q40, m31 = q31, m22 = q22, m13 = q13, m04 = q04;
     const double u2 = vx * vx + vz * vz;
     const double vxx = vx * vx, vxz = vx * vz, vzz = vz * vz;
     // contracted moments
@@ -131,6 +148,11 @@ __device__ __forceinline__ EqVjp eq_vjp_sums(const LT lam[Q], double vx, double 
 // ---------------------------------------------------------------------------
 template <bool EDGE, typename L, typename MT>
 __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0) {
+    // all-float mode (float buffers and float moments): the 15 sums and the
+    // outputs G in float, whose inputs already carry float rounding; the
+    // moments' algebra and (alpha, beta, gamma) stay double
+    using A = typename std::conditional<std::is_same<L, float>::value && std::is_same<MT, float>::value, float,
+                                        double>::type;
     const L *__restrict__ lam_in = static_cast<const L *>(a.lam_in);
     L *__restrict__ lam_out = static_cast<L *>(a.lam_out);
     const size_t N = (size_t)a.lx * (size_t)a.lz;
@@ -152,7 +174,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
                      uz = ldg_off(mcol + 2 * N, moff), T = ldg_off(mcol + 3 * N, moff);
         const double vx = ux, vz = uz - a.tau * a.g;
         const double th = T + a.tau * (1.0 - a.tau) * a.g * a.g / D - 1.0;
-        const EqVjp s = eq_vjp_sums(lam, vx, vz, th);
+        const EqVjp s = eq_vjp_sums<A>(lam, vx, vz, th);
         const double om = a.omega;
         const double mu_rho = om * s.sp;
         const double mux = om * rho * (s.sxx + 2.0 * vx * s.su2);
@@ -166,9 +188,25 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
         keep = 1.0 - om;
     }
 
+    // G_{l} and G_{l+1} (= -e_l) share alpha + gamma |xi|^2 and +-beta . xi_l
+    const A gk = (A)keep, ga = (A)alpha, gbx = (A)bx, gbz = (A)bz, gg = (A)gamma;
+    auto gval = [&](int l) -> A {
+        if (l == 0) return gk * (A)lam[0] + ga;
+        const int p = (l & 1) ? l : l - 1;
+        const A c = ga + gg * (A)XI2_SHELL[SHELL[p]];
+        A bxi;
+        if (EX[p] != 0 && EZ[p] != 0)
+            bxi = (A)EX[p] * gbx + (A)EZ[p] * gbz;
+        else if (EX[p] != 0)
+            bxi = (A)EX[p] * gbx;
+        else
+            bxi = (A)EZ[p] * gbz;
+        const A k = gk * (A)lam[l] + c;
+        return (l & 1) ? k + bxi : k - bxi;
+    };
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const L G = (L)(keep * (double)lam[l] + alpha + (EX[l] * bx + EZ[l] * bz) + gamma * XI2_SHELL[SHELL[l]]);
+        const L G = (L)gval(l);
         const int xd = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
         const int zd = z - EZ[l];
         L *dst = lam_out + (size_t)l * N + (size_t)xd * (size_t)a.lz;
@@ -186,8 +224,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
                 L park = L(0);
                 if (a.flags & F_WALL_DIFFUSE) {
                     const int o = l == 0 ? 0 : ((l & 1) ? l + 1 : l - 1);   // -e_l
-                    park = (L)(keep * (double)lam[o] + alpha + (EX[o] * bx + EZ[o] * bz) +
-                               gamma * XI2_SHELL[SHELL[o]]);
+                    park = (L)gval(o);
                 }
                 lam_out[(size_t)l * N + site] = park;
             }
@@ -205,7 +242,7 @@ constexpr int ADJ_BS = LBM_ADJ_BS, ADJ_ZT = LBM_ADJ_ZT;
 
 // L: element type of the adjoint buffers; MT: of the stored moments
 // Occupancy target: 3 wavefronts per SIMD with float buffers and float
-// moments (168 VGPRs, a few bytes of spills), 2 otherwise (165-179 VGPRs);
+// moments (140 VGPRs, no spills), 2 otherwise (165-209 VGPRs);
 // measured fastest on MI355X for the 2048 x 6144 float rollout and the
 // 512 x 1536 double rollout respectively.
 template <typename L, typename MT>
@@ -555,7 +592,7 @@ __global__ __launch_bounds__(BLOCK) void init_vjp_columns(InitVjpArgs a) {
 #pragma unroll
                 for (int l = 0; l < Q; ++l) lam[l] = (double)lam0[(size_t)l * N + site];
                 const double th = T - a.g * a.g / (4.0 * D) - 1.0;
-                const EqVjp s = eq_vjp_sums(lam, 0.0, -0.5 * a.g, th);
+                const EqVjp s = eq_vjp_sums<double>(lam, 0.0, -0.5 * a.g, th);
                 const double g_rho = s.sp, g_teq = rho * s.sth;
                 g_lp = g_rho * rho;
                 g_tdir = g_teq - g_rho * rho / T;

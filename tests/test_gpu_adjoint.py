@@ -190,20 +190,22 @@ def test_adjoint_step_float_buffers(abi, wall):
 
 
 def test_gradient_float_storage_and_adjoint_vs_f64(abi):
-    """Gradient error of the FP32 forms against the all-FP64 gradient,
-    128 x 384, 100 steps (stated; bar 1e-3 relative to the largest entry)."""
+    """Gradient error of the FP32 forms (the all-float adjoint among them)
+    against the all-FP64 gradient, 128 x 384, 100 steps (stated; bar 1e-3
+    relative to the largest entry)."""
     wl = W.WORKLOADS["rt3_128x384"]
     m = W.draw_modes(wl.seed)
     amp = torch.as_tensor(m.amp, device=DEV)
     out = {}
-    for prec, adj in (("f64", "f64"), ("f64", "f32"), ("f32dev", "f64"), ("f32dev", "f32")):
-        r = _rollout(wl, m, wl.steps, precision=prec, adj_precision=adj)
+    for prec, adj, mom in (("f64", "f64", "f64"), ("f64", "f32", "f64"), ("f32dev", "f64", "f64"),
+                           ("f32dev", "f32", "f64"), ("f32dev", "f32", "f32")):
+        r = _rollout(wl, m, wl.steps, precision=prec, adj_precision=adj, mom_precision=mom)
         J = r.forward(amp)[0].item()
-        out[prec, adj] = (J, r.backward().cpu().numpy())
-    J64, g64 = out["f64", "f64"]
+        out[prec, adj, mom] = (J, r.backward().cpu().numpy())
+    J64, g64 = out["f64", "f64", "f64"]
     for key, (J, g) in out.items():
         err = _rel_max(g, g64)
-        print(f"state {key[0]}, adjoint {key[1]}: J rel err {abs(J / J64 - 1):.2e}, "
+        print(f"state {key[0]}, adjoint {key[1]}, moments {key[2]}: J rel err {abs(J / J64 - 1):.2e}, "
               f"grad max err / max|grad| {err:.2e}")
         assert err <= 1e-3
 
@@ -232,6 +234,40 @@ def test_float_moments(abi):
     err = _rel_max(out32.cpu().numpy(), out64.cpu().numpy())
     print(f"adjoint step with float moments: {err:.2e} of max")
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("wall", ["dirichlet", "diffuse"])
+def test_adjoint_step_all_float(abi, wall):
+    """LBM_ADJ_F32 | LBM_MOM_F32: float buffers, float moments, and float
+    arithmetic for the 15 per-site sums and the outputs G.  The arithmetic
+    alone, against the double-arithmetic step on the same float inputs
+    (double lam holding the float values, the same float moments): bounded
+    by 32 float roundings of the largest entry (the sums accumulate 18 pair
+    terms rounded about three times each; G adds four roundings).  Against
+    the oracle: that bound plus the float moments' effect (1e-6 of the
+    largest entry, as in test_float_moments)."""
+    lx, lz = 128, 384
+    p, f, ghost = _state(lx, lz, 0.7, 2e-3, 23)
+    p.wall = wall
+    lam = np.random.default_rng(24).standard_normal((37, lx, lz)).astype(np.float32)
+    want = A.step_vjp(lam.astype(np.float64), f, ghost, p)
+    flags = abi.MOM_F32 | abi.wall_flag(wall)
+    fin, gh = _t(f), _t(ghost)
+    fout = torch.empty_like(fin)
+    m32 = torch.empty((4, lx, lz), dtype=torch.float32, device=DEV)
+    abi.lbm_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags), gh, fin, fout, m32)
+    out_f = torch.empty((37, lx, lz), dtype=torch.float32, device=DEV)
+    abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | abi.ADJ_F32), gh, m32, _t(lam), out_f)
+    out_d = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
+    abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags), gh, m32, _t(lam.astype(np.float64)),
+                         out_d)
+    got = out_f.cpu().numpy().astype(np.float64)
+    arith = _rel_max(got, out_d.cpu().numpy())
+    err = _rel_max(got, want)
+    print(f"all-float adjoint step ({wall}): float arithmetic {arith:.2e} of max "
+          f"({arith / 2.0 ** -24:.1f} roundings), vs oracle {err:.2e}")
+    assert arith <= 32 * 2.0 ** -24
+    assert err <= 32 * 2.0 ** -24 + 1e-6
 
 
 def test_rollout_float_moments_vs_oracle(abi):
