@@ -172,6 +172,52 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
     return out
 
 
+def propagate_pull_vs_push(wl, launches=20, rounds=2):
+    """Streaming alone, in the two forms Sec. III.B compares for the
+    propagate kernel: pull = lbm_step with LBM_NO_COLLIDE (reads shifted by
+    -e_l, aligned writes); push = lbm_adjoint_step with LBM_NO_COLLIDE, which
+    moves each input element along -e_l (aligned reads, shifted writes).
+    Both move 37 + 37 elements per site; HIP events on the current stream,
+    the two forms interleaved ``rounds`` times (means reported)."""
+    import torch
+    from paper_1405_1253_amd import abi
+    stream = torch.cuda.current_stream()
+    out = {}
+    for prec in ("f64", "f32dev"):
+        f32 = prec != "f64"
+        pr = abi.F32_DEV if f32 else abi.F64
+        p_pull = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, pr, abi.NO_COLLIDE)
+        p_push = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, pr, abi.NO_COLLIDE | (abi.ADJ_F32 if f32 else 0))
+        dt = torch.float32 if f32 else torch.float64
+        buf = [torch.rand((abi.Q, wl.lx, wl.lz), dtype=dt, device="cuda") for _ in range(2)]
+        gh = torch.rand((2, 3, abi.Q), dtype=dt, device="cuda")
+
+        def timed(fn):
+            for i in range(4):
+                fn(i)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(launches):
+                fn(i)
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / launches / 1e3
+
+        t = {"pull": [], "push": []}
+        for _ in range(rounds):
+            t["pull"].append(timed(lambda i: abi.lbm_step(p_pull, gh, buf[i % 2], buf[1 - i % 2])))
+            t["push"].append(timed(lambda i: abi.lbm_adjoint_step(p_push, gh, None, buf[i % 2], buf[1 - i % 2])))
+        del buf, gh
+        torch.cuda.empty_cache()
+        nbytes = bytes_per_site(prec) * wl.lx * wl.lz
+        for form, ts in t.items():
+            sec = sum(ts) / len(ts)
+            out[f"{prec}_{form}_ms"] = round(sec * 1e3, 4)
+            out[f"{prec}_{form}_hbm_gbs"] = round(nbytes / sec / 1e9, 1)
+        out[f"{prec}_pull_over_push"] = round(out[f"{prec}_pull_hbm_gbs"] / out[f"{prec}_push_hbm_gbs"], 3)
+    return out
+
+
 def copy_calibration(nbytes=4 << 30, reps=3):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -259,6 +305,7 @@ def main():
                         f"{key}_hbm_gbs": round(a2, 1),
                         f"{key}_frac": round(a2 / HBM_PEAK_GBS, 4)})
         out["secondary"] = sec
+        out["propagate_pull_vs_push"] = propagate_pull_vs_push(wl)
     if not args.no_adjoint:
         out["adjoint"] = [adjoint_ratio("rt3_512x1536_adj"),
                           adjoint_ratio("rt3_512x1536_adj_diffuse"),
