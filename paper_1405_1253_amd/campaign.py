@@ -10,6 +10,7 @@ T and E_k (Figs. 6, 8 and 9); only these small arrays come back to the host.
 alpha_tot = Ldot_tot^2 / (4 At g L_tot) (the self-similar form of eq. eqL2).
 """
 import argparse
+import dataclasses
 import json
 import sys
 import time
@@ -81,15 +82,19 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=1000)
     ap.add_argument("--profiles-at", type=str, default="0,1,2,3,4",
                     help="RT times at which to record the row profiles")
+    ap.add_argument("--seed", type=int, default=None,
+                    help="seed of the interface modes (default: the workload's); one realisation per seed")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     from . import abi
     wl = WORKLOADS[args.workload]
+    if args.seed is not None:
+        wl = dataclasses.replace(wl, seed=args.seed)
     tau = rt_time(wl, abi.lbm_lattice()[0])
     nsteps = int(round(args.tau_rt * tau / args.every)) * args.every
     ptimes = [int(round(float(x) * tau / args.every)) * args.every for x in args.profiles_at.split(",")]
     ptimes = [p for p in ptimes if p <= nsteps]
-    print(json.dumps({"workload": wl.name, "tau_rt_steps": tau, "nsteps": nsteps}), flush=True)
+    print(json.dumps({"workload": wl.name, "seed": wl.seed, "tau_rt_steps": tau, "nsteps": nsteps}), flush=True)
 
     def progress(t, L, s):
         print(f"step {t} (t/tau {t / tau:.2f}): L_tot {L:.1f}, {s:.0f} s", flush=True)
