@@ -10,7 +10,10 @@ three-layer Rayleigh-Taylor lattice of one GPU's production share,
 4096 x 12288 sites.  Prints one JSON line with MLUPS, the HBM roofline of the
 step kernel (algorithmic bytes / kernel time, timed with HIP events on the
 stream the kernel runs on) and the CPU oracle timed on a bounded sample.
-The same lattice in FP32 deviation storage is timed as a secondary figure.
+Secondary figures: the same lattice in FP32 deviation storage, with the
+diffuse (mass-conserving) walls and on a single buffer, both precisions;
+streaming alone in pull and in push form; the adjoint rollouts' cost
+relative to a plain forward.
 """
 import argparse
 import hashlib
