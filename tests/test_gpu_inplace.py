@@ -215,3 +215,24 @@ def test_largest_lattice_single_buffer(abi):
           f"lbm_moments mass vs a plain sum {abs(mass / total - 1):.1e}; {ms:.1f} ms/step, {gbs:.0f} GB/s")
     assert worst[0] <= 1e-12 and worst[2] <= 1e-12
     assert abs(mass / total - 1) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32dev"])
+def test_in_place_float_moments(abi, prec):
+    """LBM_MOM_F32 on a single buffer: the first step's float moments equal
+    the two-buffer step's bit for bit (same input), and they are the double
+    moments rounded to float."""
+    base = abi.F64 if prec == "f64" else abi.F32_DEV
+    p32 = abi.make_params(64, 200, 0.7, 2.6e-4, base, abi.MOM_F32)
+    p64 = abi.make_params(64, 200, 0.7, 2.6e-4, base, 0)
+    _, f0, gh = _init(abi, p32, 77)
+    m_in = torch.empty((4, 64, 200), dtype=torch.float32, device=DEV)
+    f = f0.clone()
+    abi.lbm_step_inplace(p32, gh, f, abi.INPLACE_FROM_STATE, m_in, _scratch(abi, p32))
+    m_two = torch.empty_like(m_in)
+    m_dbl = torch.empty((4, 64, 200), dtype=torch.float64, device=DEV)
+    out = torch.empty_like(f0)
+    abi.lbm_step(p32, gh, f0, out, m_two)
+    abi.lbm_step(p64, gh, f0, out, m_dbl)
+    assert torch.equal(m_in, m_two)
+    assert torch.equal(m_in, m_dbl.float())
