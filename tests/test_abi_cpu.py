@@ -151,3 +151,34 @@ def test_error_strings(abi):
     lib = abi.load()
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert lib.lbm_strerror(code)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without liblbm.so every entry into the product raises: there is no CPU
+    fallback (run in a fresh interpreter so the loaded library of the other
+    tests is untouched)."""
+    code = f"""
+import sys
+sys.path.insert(0, {ROOT!r})
+from paper_1405_1253_amd import abi
+abi._LIB = None
+abi.LIB_PATH = {str(tmp_path / "liblbm.so")!r}
+p = abi.make_params(8, 8, 0.7, 1e-4)          # a host struct: no library needed
+for call in (abi.load, lambda: abi.lbm_scratch_bytes(p), lambda: abi.lbm_step(p, None, None, None)):
+    try:
+        call()
+    except ImportError as e:
+        assert "no CPU fallback" in str(e), e
+    else:
+        raise SystemExit("no error without the library")
+from paper_1405_1253_amd.runtime import Lattice
+try:
+    Lattice(8, 8, 0.7, 1e-4, device="cpu")
+except ImportError:
+    pass
+else:
+    raise SystemExit("Lattice built without the library")
+print("ok")
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
