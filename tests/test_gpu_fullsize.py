@@ -29,8 +29,11 @@ def _oracle_column(wl, m, x, nsteps):
     return f[:, half, :], ghost
 
 
-@pytest.mark.parametrize("name,tol", [("rt3_4096x12288", 1e-12), ("rt3_4096x12288_f32", 5e-7)])
+@pytest.mark.parametrize("name,tol", [("rt3_4096x12288", 1e-12), ("rt3_4096x12288_f32", 5e-7),
+                                      ("rt3_4096x12288_inplace", 1e-12), ("rt3_4096x12288_f32_inplace", 5e-7)])
 def test_fullsize_sampled_columns(name, tol):
+    """Both storage forms, on two buffers and on one (the single buffer holds
+    the state only after an even number of steps: sampled after 0 and 2)."""
     from paper_1405_1253_amd.runtime import Lattice
     wl = W.WORKLOADS[name]
     m = W.draw_modes(wl.seed)
@@ -46,10 +49,14 @@ def test_fullsize_sampled_columns(name, tol):
         return c + w[:, None] if w is not None else c
 
     got = {0: {x: column(x) for x in SAMPLES}}
-    lat.step(1)
-    got[1] = {x: column(x) for x in SAMPLES}
-    lat.step(1)
-    got[2] = {x: column(x) for x in (0, 2048, 4095)}
+    if wl.inplace:
+        lat.step(2)
+        got[2] = {x: column(x) for x in SAMPLES}
+    else:
+        lat.step(1)
+        got[1] = {x: column(x) for x in SAMPLES}
+        lat.step(1)
+        got[2] = {x: column(x) for x in (0, 2048, 4095)}
     lat.sums()
     del lat
     torch.cuda.empty_cache()
@@ -60,11 +67,12 @@ def test_fullsize_sampled_columns(name, tol):
             want, ghost = _oracle_column(wl, m, x, n)
             worst[n] = max(worst.get(n, 0.0), float(np.max(np.abs(g - want) / want)))
     ghost_full = ghost_gpu + (w[None, None, :] if w is not None else 0.0)
-    print(f"{name}: max rel err over sampled columns: init {worst[0]:.2e}, "
-          f"1 step {worst[1]:.2e}, 2 steps {worst[2]:.2e}")
+    print(f"{name}: max rel err over sampled columns: "
+          + ", ".join(f"{n} steps {e:.2e}" for n, e in sorted(worst.items())))
     assert float(np.max(np.abs(ghost_full - ghost) / ghost)) <= (1e-13 if w is None else 2.0 ** -24)
-    for n in (0, 1, 2):
-        assert worst[n] <= tol, (n, worst[n])
+    for n, e in worst.items():
+        # FP32: the per-step deviation bound, growing at most linearly
+        assert e <= tol * (max(n, 1) if w is not None else 1), (n, e)
 
 
 def test_fullsize_bitwise_reproducible():
