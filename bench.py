@@ -234,6 +234,37 @@ def copy_calibration(nbytes=4 << 30, reps=3):
                       "launches": reps}), flush=True)
 
 
+def adjoint_counter_run(launches=6):
+    """A short sequence for the HBM counters of the adjoint step: at the
+    2048 x 6144 float rollout's shape, ``launches`` all-float adjoint steps
+    (float buffers and moments) and then ``launches`` streaming-only ones."""
+    import torch
+    from paper_1405_1253_amd import abi
+    from paper_1405_1253_amd.workload import WORKLOADS, draw_modes
+    wl = WORKLOADS["rt3_2048x6144_adj"]
+    m = draw_modes(wl.seed)
+    base = abi.F32_DEV
+    p_fwd = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, base, abi.MOM_F32)
+    p_adj = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, base, abi.MOM_F32 | abi.ADJ_F32)
+    p_str = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, base, abi.NO_COLLIDE | abi.ADJ_F32)
+    shape = (abi.Q, wl.lx, wl.lz)
+    f = torch.empty(shape, dtype=torch.float32, device="cuda")
+    gh = torch.empty((2, 3, abi.Q), dtype=torch.float32, device="cuda")
+    abi.lbm_init_rt3(p_fwd, abi.RT3Desc(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase),
+                     torch.as_tensor(m.amp, device="cuda"), f, gh)
+    mom = torch.empty((4, wl.lx, wl.lz), dtype=torch.float32, device="cuda")
+    abi.lbm_step(p_fwd, gh, f, torch.empty_like(f), mom)
+    gen = torch.Generator(device="cuda").manual_seed(wl.seed)
+    lam = [torch.randn(shape, dtype=torch.float32, device="cuda", generator=gen), torch.empty_like(f)]
+    for i in range(launches):
+        abi.lbm_adjoint_step(p_adj, gh, mom, lam[i % 2], lam[1 - i % 2])
+    for i in range(launches):
+        abi.lbm_adjoint_step(p_str, gh, None, lam[i % 2], lam[1 - i % 2])
+    torch.cuda.synchronize()
+    print(json.dumps({"adjoint_counter_run": wl.name, "sites": wl.lx * wl.lz,
+                      "launches_all_float": launches, "launches_streaming_only": launches}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,9 +276,14 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for the HBM counters)")
+    ap.add_argument("--adjoint-counter-run", action="store_true",
+                    help="only run a short adjoint sequence (for the HBM counters)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.adjoint_counter_run:
+        adjoint_counter_run()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU x-slab "
