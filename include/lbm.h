@@ -308,7 +308,8 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  * LBM_MOM_F32 (all inputs float): then the per-site sums of lam_in against
  * the 15 monomials xi_x^p xi_z^q (p + q <= 4) and the outputs G_l are formed
  * in float, and the moments' algebra and (alpha, beta, gamma) in double
- * (error about 10 float roundings of the largest output).  params->precision
+ * (error within 32 float roundings of the largest output; about 5 on random
+ * inputs).  params->precision
  * names the forward state it belongs to and the element type of ghost.
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
  */
