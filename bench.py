@@ -45,6 +45,28 @@ def step_source_hash():
     return h.hexdigest()[:16]
 
 
+def adjoint_source_hash():
+    h = hashlib.sha256()
+    for name in ("adjoint.hip", "common.h", "lattice_constants.h"):
+        with open(os.path.join(ROOT, "paper_1405_1253_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_adjoint_traffic(workload):
+    """HBM bytes per all-float adjoint launch from the committed counter
+    summary, if it was taken on the current adjoint source (else None)."""
+    path = os.path.join(PROFILES, f"adjoint_f32_{workload.replace('_adj', '')}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"adjoint_source_sha:\s*(\w+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_src or not m_b or m_src.group(1) != adjoint_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
 def measured_traffic(workload, precision):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source (else None)."""
@@ -169,6 +191,8 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
            "adjoint_step_ms": round(t_adj * 1e3, 4),
            "adjoint_step_over_forward_step": round(t_adj / (plain / wl.steps), 3),
            "adjoint_hbm_gbs": round(adj_gbs, 1), "adjoint_frac": round(adj_gbs / HBM_PEAK_GBS, 4),
+           "adjoint_traffic": (measured_adjoint_traffic(name)
+                               if r.lam[0].dtype == torch.float32 and mom.dtype == torch.float32 else None),
            "grad_finite": bool(torch.isfinite(grad).all().item())}
     del r, mom
     torch.cuda.empty_cache()

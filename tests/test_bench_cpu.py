@@ -52,3 +52,15 @@ def test_source_hash_covers_the_step_sources(name, monkeypatch, tmp_path):
     with open(csrc / name, "ab") as fh:
         fh.write(b"\n")
     assert bench.step_source_hash() != h0
+
+
+def test_adjoint_traffic_only_for_the_profiled_source(monkeypatch):
+    path = os.path.join(ROOT, "profiles", "adjoint_f32_rt3_2048x6144_counters.txt")
+    sha = open(path).read().split("adjoint_source_sha:")[1].split()[0]
+    monkeypatch.setattr(bench, "adjoint_source_hash", lambda: sha)
+    b = bench.measured_adjoint_traffic("rt3_2048x6144_adj")
+    alg = (37 * 4 + 4 * 4 + 37 * 4) * 2048 * 6144      # float lam in and out, float moments
+    assert b is not None and alg <= b <= 1.1 * alg
+    assert bench.measured_adjoint_traffic("rt3_512x1536_adj") is None      # not profiled
+    monkeypatch.setattr(bench, "adjoint_source_hash", lambda: "0" * 16)
+    assert bench.measured_adjoint_traffic("rt3_2048x6144_adj") is None
