@@ -182,3 +182,27 @@ print("ok")
 """
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+def header_constants():
+    """#define and enum values of include/lbm.h (comments stripped)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {k: int(v) for k, v in re.findall(r"#define\s+(LBM_[A-Z0-9_]+)\s+(-?\d+)u?\b", text)}
+    for body in re.findall(r"enum\s+\w+\s*\{(.*?)\}", text, flags=re.S):
+        for k, v in re.findall(r"(LBM_[A-Z0-9_]+)\s*=\s*(-?\d+)u?", body):
+            out[k] = int(v)
+    return out
+
+
+def test_binding_constants_match_the_header():
+    """The ctypes binding's numbers are the header's: ABI version, sizes,
+    precisions, flags, in-place kinds and status codes."""
+    from paper_1405_1253_amd import abi as mod
+    h = header_constants()
+    assert h["LBM_ABI_VERSION"] == mod.ABI_VERSION and h["LBM_Q"] == mod.Q
+    assert h["LBM_MAX_MODES"] == mod.MAX_MODES
+    for name in ("F64", "F32_DEV", "PERIODIC_Z", "NO_COLLIDE", "ADJ_F32", "WALL_DIFFUSE", "MOM_F32",
+                 "INPLACE_FROM_STATE", "INPLACE_FROM_STREAMED"):
+        assert h["LBM_" + name] == getattr(mod, name), name
+    status = {v: k for k, v in h.items() if k in ("LBM_OK",) or (k.startswith("LBM_E") and v < 0)}
+    assert status == mod.STATUS
