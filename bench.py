@@ -97,31 +97,108 @@ def time_steps(lat, steps, warmup):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def cpu_baseline(wl, columns=32, min_seconds=10.0, max_steps=64):
-    """The oracle on a strip of the same workload: `columns` full-height
-    columns of the lattice, periodic across the strip, stepped until at least
-    `min_seconds` of CPU time (at least 2 steps, at most `max_steps`)."""
+def interleaved_windows(lat, windows=5, k=20):
+    """The fused step and streaming alone (LBM_NO_COLLIDE) on the same two
+    buffers of ``lat``, alternating windows of ``k`` launches (HIP events on
+    the current stream): median, min and max ms per launch of each, and the
+    ratio of the medians (the cost of the collision over the pattern's own)."""
+    import statistics
+
+    import torch
+    from paper_1405_1253_amd import abi
+    p = lat.params
+    p_nc = abi.make_params(p.lx, p.lz, p.tau, p.g, p.precision, p.flags | abi.NO_COLLIDE)
+    stream = torch.cuda.current_stream()
+
+    def window(params):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            abi.lbm_step(params, lat.ghost, lat.buf[lat.cur], lat.buf[1 - lat.cur])
+            lat.cur = 1 - lat.cur
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    window(p_nc)
+    t = {"fused": [], "streaming": []}
+    for _ in range(windows):
+        t["fused"].append(window(p))
+        t["streaming"].append(window(p_nc))
+    out = {}
+    for key, ts in t.items():
+        out[f"{key}_ms"] = {"median": round(statistics.median(ts), 4), "min": round(min(ts), 4),
+                            "max": round(max(ts), 4)}
+    out["fused_over_streaming"] = round(statistics.median(t["fused"]) / statistics.median(t["streaming"]), 4)
+    out["windows"], out["launches_per_window"] = windows, k
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_strip_worker(name, x0, columns, min_seconds, max_steps, barrier, out):
+    """One host core: the oracle on its own strip of `columns` full-height
+    columns of the workload (periodic across the strip), one BLAS/OpenMP
+    thread, stepped for at least `min_seconds` once every worker is ready."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import lbm as O
-    from paper_1405_1253_amd.workload import draw_modes
+    from paper_1405_1253_amd.workload import WORKLOADS, draw_modes
+    wl = WORKLOADS[name]
     m = draw_modes(wl.seed)
-    p_full = O.Params(wl.lx, wl.lz, wl.tau, wl.g)
-    desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
-    f, ghost = O.init_rt3(p_full, desc, m.amp, columns=np.arange(columns))
-    p = O.Params(columns, wl.lz, wl.tau, wl.g)
-    steps = 0
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
+        p_full = O.Params(wl.lx, wl.lz, wl.tau, wl.g)
+        desc = O.RT3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase)
+        f, ghost = O.init_rt3(p_full, desc, m.amp, columns=np.arange(x0, x0 + columns))
+        p = O.Params(columns, wl.lz, wl.tau, wl.g)
+        barrier.wait()
+        steps, t0 = 0, time.perf_counter()
         while steps < max_steps and (steps < 2 or time.perf_counter() - t0 < min_seconds):
             f = O.step(f, ghost, p)
             steps += 1
         dt = time.perf_counter() - t0
-    return {"value": columns * wl.lz * steps / dt / 1e6, "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} steps of a {columns} x {wl.lz} column strip of the {wl.name} "
-                      f"lattice (numpy FP64 oracle, 1 thread, {dt:.1f} s)"}
+    out.put((x0, steps, dt, columns * wl.lz))
+
+
+def cpu_baseline(wl, columns=32, min_seconds=12.0, max_steps=64, max_workers=16):
+    """The oracle on the host cores: one process per core (at most
+    ``max_workers``, the host share of one GPU), each stepping its own strip
+    of `columns` full-height columns of the same workload, all at once.  The
+    rate is the sum of the workers' site updates per second.  Runs before
+    anything touches the GPU (the workers are started by spawning fresh
+    interpreters)."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), max_workers, max(1, wl.lx // columns))
+    ctx = mp.get_context("spawn")
+    barrier, out = ctx.Barrier(cores), ctx.Queue()
+    procs = [ctx.Process(target=_oracle_strip_worker,
+                         args=(wl.name, i * columns, columns, min_seconds, max_steps, barrier, out))
+             for i in range(cores)]
+    for pr in procs:
+        pr.start()
+    res = [out.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+        if pr.exitcode != 0:
+            raise RuntimeError(f"oracle worker exited with {pr.exitcode}")
+    rate = sum(steps * sites / dt for _, steps, dt, sites in res)
+    steps = sorted(r[1] for r in res)
+    secs = max(r[2] for r in res)
+    return {"value": rate / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "sample": f"{cores} processes, one per core, each stepping its own {columns} x {wl.lz} column "
+                      f"strip of the {wl.name} lattice ({steps[0]}-{steps[-1]} steps, {secs:.1f} s; numpy "
+                      f"FP64 oracle, one thread per process); rate = sum of the processes' rates"}
 
 
 def adjoint_ratio(name, budget_bytes=None, warm=True):
@@ -187,6 +264,7 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
            "backward_over_plain_forward": round(t_bwd / plain, 3),
            "gradient_over_plain_forward": round((t_fwd + t_bwd) / plain, 3),
            "recomputed_steps": r.recomputed_steps, "moments_kept": r.keep,
+           "ckpt_every": r.ckpt_every, "state_checkpoints": len(r.ckpt),
            "moments_dtype": str(mom.dtype).replace("torch.", ""),
            "adjoint_step_ms": round(t_adj * 1e3, 4),
            "adjoint_step_over_forward_step": round(t_adj / (plain / wl.steps), 3),
@@ -314,13 +392,17 @@ def main():
               "decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
+    from paper_1405_1253_amd.workload import WORKLOADS
+    wl = WORKLOADS[args.workload]
+    # the host-core oracle first: its worker processes start before this
+    # process initialises the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+
     import torch
     from paper_1405_1253_amd import abi
     from paper_1405_1253_amd.runtime import Lattice
-    from paper_1405_1253_amd.workload import WORKLOADS
 
     abi.load()
-    wl = WORKLOADS[args.workload]
     lat = Lattice.from_workload(wl)
     secs, wall = time_steps(lat, args.steps, args.warmup)
     lat.sums()                                       # raises on a diverged state
@@ -330,6 +412,8 @@ def main():
     bpl = bytes_per_site(wl.precision) * sites
     achieved = bpl / (secs / args.steps) / 1e9
     traffic = measured_traffic(wl.name, wl.precision)
+    windows = None if args.no_secondary else interleaved_windows(lat)
+    lat.sums()
     del lat
     torch.cuda.empty_cache()
 
@@ -345,6 +429,8 @@ def main():
                      "traffic": traffic, "bytes_per_launch": bpl,
                      "kernel": "lbm::step_kernel", "wall_s": round(wall, 3)},
     }
+    if windows is not None:
+        out["fused_vs_streaming"] = windows
     if not args.no_secondary and wl.precision == "f64":
         # the same lattice in FP32 deviation storage, both precisions with the
         # diffuse (mass-conserving) wall rule, and both on a single buffer
@@ -359,6 +445,8 @@ def main():
             n2 = args.steps + (args.steps % 2 if w2.inplace else 0)
             lat = Lattice.from_workload(w2)
             s2, _ = time_steps(lat, n2, args.warmup + (args.warmup % 2 if w2.inplace else 0))
+            if key == "f32dev":
+                out["fused_vs_streaming_f32dev"] = interleaved_windows(lat)
             lat.sums()
             del lat
             torch.cuda.empty_cache()
@@ -370,11 +458,15 @@ def main():
         out["secondary"] = sec
         out["propagate_pull_vs_push"] = propagate_pull_vs_push(wl)
     if not args.no_adjoint:
+        c4 = WORKLOADS["rt3_512x1536_adj"]
         out["adjoint"] = [adjoint_ratio("rt3_512x1536_adj"),
+                          # the same rollout with moments for one 100-step segment only: the
+                          # backward sweep recomputes each segment from its state checkpoint
+                          adjoint_ratio("rt3_512x1536_adj", c4.ckpt_every * 4 * c4.lx * c4.lz * 8),
                           adjoint_ratio("rt3_512x1536_adj_diffuse"),
                           adjoint_ratio("rt3_2048x6144_adj", 232 << 30, warm=False)]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,9 @@
 """ctypes binding of liblbm.so: the C entry points under the same names.
 
 Argument marshalling only -- every step of the method runs in the library's
-HIP kernels.  Buffers are torch tensors (device memory) or raw integer
+HIP kernels.  Before a call, each tensor's element type and size are checked
+against what the parameters imply (the C entry points see only addresses),
+so a mismatched buffer raises ValueError instead of being overrun.  Buffers are torch tensors (device memory) or raw integer
 addresses; streams default to torch's current stream.  A failing call raises
 LbmError with the library's status text.  Loading fails loudly when the
 library has not been built: there is no fallback.
@@ -114,6 +116,45 @@ def _ptr(x):
     return x.data_ptr()
 
 
+def _sites(params):
+    return int(params.lx) * int(params.lz)
+
+
+def _state_dtype(params):
+    import torch
+    return torch.float64 if params.precision == F64 else torch.float32
+
+
+def _lam_dtype(params):
+    import torch
+    return torch.float32 if params.flags & ADJ_F32 else torch.float64
+
+
+def _mom_dtype(params):
+    import torch
+    return torch.float32 if params.flags & MOM_F32 else torch.float64
+
+
+def _need(name, x, dtype, numel):
+    """Host-side check of one buffer against what the parameters imply.
+
+    The C entry points see only addresses, so a tensor of the wrong element
+    type or too few elements would be read or written past its end on the
+    device; this raises ValueError before anything is launched.  Raw integer
+    addresses are passed through unchecked (the caller vouches for them)."""
+    if x is None or isinstance(x, int):
+        return
+    if x.dtype != dtype:
+        raise ValueError(f"{name}: dtype {x.dtype}, expected {dtype} for these parameters")
+    if x.numel() < numel:
+        raise ValueError(f"{name}: {x.numel()} elements, expected at least {numel} for these parameters")
+
+
+def _f64():
+    import torch
+    return torch.float64
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -150,6 +191,9 @@ def lbm_init_rt3(params, desc, amp, f_out, ghost_out, stream=None):
     """Three-layer hydrostatic initial state (see include/lbm.h).
 
     desc: RT3Desc (host k, phase [2, nmodes]); amp: device float64 [2, nmodes]."""
+    _need("amp", amp, _f64(), 2 * desc.nmodes)
+    _need("f_out", f_out, _state_dtype(params), Q * _sites(params))
+    _need("ghost_out", ghost_out, _state_dtype(params), 2 * 3 * Q)
     st = load().lbm_init_rt3(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(f_out),
                              _ptr(ghost_out), _stream(stream))
     _check(st, "lbm_init_rt3")
@@ -157,6 +201,10 @@ def lbm_init_rt3(params, desc, amp, f_out, ghost_out, stream=None):
 
 def lbm_step(params, ghost, f_in, f_out, moments_out=None, stream=None):
     """One fused propagate + bc + collide step (see include/lbm.h)."""
+    _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
+    _need("f_in", f_in, _state_dtype(params), Q * _sites(params))
+    _need("f_out", f_out, _state_dtype(params), Q * _sites(params))
+    _need("moments_out", moments_out, _mom_dtype(params), 4 * _sites(params))
     st = load().lbm_step(ctypes.byref(params), _ptr(ghost), _ptr(f_in), _ptr(f_out),
                          _ptr(moments_out), _stream(stream))
     _check(st, "lbm_step")
@@ -165,6 +213,9 @@ def lbm_step(params, ghost, f_in, f_out, moments_out=None, stream=None):
 def lbm_step_inplace(params, ghost, f, kind, moments_out=None, scratch=None, stream=None):
     """One step on a single buffer, kind INPLACE_FROM_STATE or
     INPLACE_FROM_STREAMED (see include/lbm.h)."""
+    _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
+    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("moments_out", moments_out, _mom_dtype(params), 4 * _sites(params))
     st = load().lbm_step_inplace(ctypes.byref(params), _ptr(ghost), _ptr(f), int(kind), _ptr(moments_out),
                                  _ptr(scratch), _nbytes(scratch), _stream(stream))
     _check(st, "lbm_step_inplace")
@@ -176,6 +227,10 @@ def lbm_scratch_bytes(params):
 
 def lbm_moments(params, f, fields=None, tbar=None, sums=None, scratch=None, stream=None):
     """Renormalised fields, mean profile and global sums (see include/lbm.h)."""
+    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("fields", fields, _f64(), 4 * _sites(params))
+    _need("tbar", tbar, _f64(), int(params.lz))
+    _need("sums", sums, _f64(), 4)
     nbytes = 0 if scratch is None else scratch.numel() * scratch.element_size()
     st = load().lbm_moments(ctypes.byref(params), _ptr(f), _ptr(fields), _ptr(tbar), _ptr(sums),
                             _ptr(scratch), nbytes, _stream(stream))
@@ -198,6 +253,9 @@ def _nbytes(t):
 def lbm_objective(params, desc, f, wk, wl, j_out, lam_seed=None, scratch=None, stream=None):
     """J = wk KE + wl (L_u + L_d) into j_out[5] = (J, KE, L_u + L_d, L_u, L_d) and
     optionally dJ/df (see include/lbm.h)."""
+    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("j_out", j_out, _f64(), 5)
+    _need("lam_seed", lam_seed, _lam_dtype(params), Q * _sites(params))
     st = load().lbm_objective(ctypes.byref(params), ctypes.byref(desc.c), _ptr(f), wk, wl,
                               _ptr(j_out), _ptr(lam_seed), _ptr(scratch), _nbytes(scratch),
                               _stream(stream))
@@ -207,6 +265,10 @@ def lbm_objective(params, desc, f, wk, wl, j_out, lam_seed=None, scratch=None, s
 def lbm_adjoint_step(params, ghost, moments, lam_in, lam_out, stream=None):
     """lam_out = (d step / d f_in)^T lam_in (see include/lbm.h).  ``ghost`` is
     the forward step's wall table (needed with WALL_DIFFUSE, else may be None)."""
+    _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
+    _need("moments", moments, _mom_dtype(params), 4 * _sites(params))
+    _need("lam_in", lam_in, _lam_dtype(params), Q * _sites(params))
+    _need("lam_out", lam_out, _lam_dtype(params), Q * _sites(params))
     st = load().lbm_adjoint_step(ctypes.byref(params), _ptr(ghost), _ptr(moments), _ptr(lam_in),
                                  _ptr(lam_out), _stream(stream))
     _check(st, "lbm_adjoint_step")
@@ -214,6 +276,9 @@ def lbm_adjoint_step(params, ghost, moments, lam_in, lam_out, stream=None):
 
 def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):
     """d_amp = (d init / d amp)^T lam0 (see include/lbm.h)."""
+    _need("amp", amp, _f64(), 2 * desc.nmodes)
+    _need("lam0", lam0, _lam_dtype(params), Q * _sites(params))
+    _need("d_amp", d_amp, _f64(), 2 * desc.nmodes)
     st = load().lbm_init_rt3_vjp(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(lam0),
                                  _ptr(d_amp), _ptr(scratch), _nbytes(scratch), _stream(stream))
     _check(st, "lbm_init_rt3_vjp")
@@ -221,6 +286,8 @@ def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):
 
 def lbm_profiles(params, f, prof, scratch, stream=None):
     """Row means and rms fluctuations of T^H and E_k into prof [4, Lz] (see include/lbm.h)."""
+    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("prof", prof, _f64(), 4 * int(params.lz))
     st = load().lbm_profiles(ctypes.byref(params), _ptr(f), _ptr(prof), _ptr(scratch),
                              _nbytes(scratch), _stream(stream))
     _check(st, "lbm_profiles")

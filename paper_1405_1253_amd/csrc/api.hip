@@ -1,11 +1,9 @@
 // C ABI of the D2Q37 library: argument validation, host-side set-up and
-// dispatch to the kernels.  No allocation, no synchronisation, no global
-// mutable state except the per-thread text of the last HIP error.
+// dispatch to the kernels.  No allocation (device or host), no
+// synchronisation, no global mutable state except the per-thread text of
+// the last HIP error (a fixed buffer).
 #include <math.h>
 #include <string.h>
-
-#include <string>
-#include <vector>
 
 #include "../../include/lbm.h"
 #include "common.h"
@@ -13,11 +11,13 @@
 
 namespace {
 
-thread_local std::string g_last_hip_error;
+thread_local char g_last_hip_error[256];
 
 int hip_status(hipError_t e) {
     if (e == hipSuccess) return LBM_OK;
-    g_last_hip_error = hipGetErrorString(e);
+    const char *msg = hipGetErrorString(e);
+    strncpy(g_last_hip_error, msg ? msg : "unknown HIP error", sizeof(g_last_hip_error) - 1);
+    g_last_hip_error[sizeof(g_last_hip_error) - 1] = '\0';
     return LBM_EHIP;
 }
 
@@ -73,27 +73,34 @@ void rest_heights(const lbm_params *p, const lbm_rt3_desc *d, double *lo, double
 
 void host_profile(const lbm_params *p, const lbm_rt3_desc *d, double *norm, double ghost_rho[6],
                   double ghost_t[6]) {
+    // one pass over rows -3 .. Lz+2 (index i = row + 3), no buffers: the
+    // log-pressure recursion needs only the previous row's temperature
     const int lz = p->lz, n = lz + 6;
     double z_lo, z_hi;
     rest_heights(p, d, &z_lo, &z_hi);
-    std::vector<double> T(n), lnp(n);
-    for (int i = 0; i < n; ++i) {
+    auto temp = [&](int i) {
         const double zc = (double)(i - 3) + 0.5;
         const double s0 = 0.5 * (1.0 + tanh((zc - z_lo) / d->width));
         const double s1 = 0.5 * (1.0 + tanh((zc - z_hi) / d->width));
-        T[i] = d->t_d + (d->t_m - d->t_d) * s0 + (d->t_u - d->t_m) * s1;
+        return d->t_d + (d->t_m - d->t_d) * s0 + (d->t_u - d->t_m) * s1;
+    };
+    const int rows[6] = {2, 1, 0, 3 + lz, 4 + lz, 5 + lz};   // -1,-2,-3, Lz,Lz+1,Lz+2
+    double ghost_lnp[6] = {0, 0, 0, 0, 0, 0};
+    double mean = 0.0, lnp = 0.0, t_prev = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double T = temp(i);
+        if (i > 0) lnp = lnp - p->g * lbm::R * 0.5 * (1.0 / t_prev + 1.0 / T);
+        if (i >= 3 && i < 3 + lz) mean += exp(lnp) / T;
+        for (int k = 0; k < 6; ++k)
+            if (rows[k] == i) {
+                ghost_lnp[k] = lnp;
+                ghost_t[k] = T;
+            }
+        t_prev = T;
     }
-    lnp[0] = 0.0;
-    for (int i = 1; i < n; ++i) lnp[i] = lnp[i - 1] - p->g * lbm::R * 0.5 * (1.0 / T[i - 1] + 1.0 / T[i]);
-    double mean = 0.0;
-    for (int i = 3; i < 3 + lz; ++i) mean += exp(lnp[i]) / T[i];
     mean /= (double)lz;
     *norm = 1.0 / mean;
-    const int rows[6] = {2, 1, 0, 3 + lz, 4 + lz, 5 + lz};   // -1,-2,-3, Lz,Lz+1,Lz+2
-    for (int i = 0; i < 6; ++i) {
-        ghost_t[i] = T[rows[i]];
-        ghost_rho[i] = *norm * exp(lnp[rows[i]]) / T[rows[i]];
-    }
+    for (int k = 0; k < 6; ++k) ghost_rho[k] = *norm * exp(ghost_lnp[k]) / ghost_t[k];
 }
 
 // Checks shared by the entry points that take an lbm_rt3_desc.
@@ -133,7 +140,7 @@ const char *lbm_strerror(int status) {
     }
 }
 
-const char *lbm_last_hip_error(void) { return g_last_hip_error.c_str(); }
+const char *lbm_last_hip_error(void) { return g_last_hip_error; }
 
 int lbm_lattice(double *r, double *w, int32_t *e) {
     if (r) *r = lbm::R;

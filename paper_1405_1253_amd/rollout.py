@@ -7,8 +7,9 @@ lbm_init_rt3_vjp); this module only schedules them and manages memory.
 
 Memory schedule (two levels):
 * level 1 -- the state f*_t is checkpointed every ``ckpt_every`` steps during
-  the forward pass (the initial state is checkpoint 0); ``ckpt_every = 0``
-  sets the interval to the number of kept steps, the largest segment the
+  the forward pass (the initial state is checkpoint 0), also where every
+  step's moments are kept and no segment will be recomputed; ``ckpt_every =
+  0`` sets the interval to the number of kept steps, the largest segment the
   kept buffer can hold, which needs the fewest checkpoints;
 * level 2 -- the adjoint of step t needs the 4 pre-collision moments of that
   step (double, or float with ``mom_precision="f32"``).  The forward pass
@@ -65,10 +66,13 @@ class RolloutConfig:
 
 def checkpoint_steps(nsteps, keep, ckpt_every):
     """Steps after which the forward pass stores the state (0 = the initial
-    state): every ``ckpt_every`` steps, up to the first step whose moments
-    are kept."""
-    first_kept = nsteps - keep + 1
-    return [0] + [t for t in range(ckpt_every, nsteps, ckpt_every) if t < first_kept]
+    state): every ``ckpt_every`` steps of the run, whether or not the
+    backward sweep will recompute from them (with every step's moments kept
+    none is needed for the gradient; they are the run's restart points).
+    ``keep`` does not change the schedule; it is taken for symmetry with
+    backward_plan."""
+    del keep
+    return [0] + list(range(ckpt_every, nsteps, ckpt_every))
 
 
 def backward_plan(nsteps, keep, ckpt_every):
@@ -129,6 +133,12 @@ class Rollout:
     def _step(self, src, dst, mom=None):
         abi.lbm_step(self.params, self.ghost, src, dst, mom)
 
+    def _save(self, t, state):
+        # checkpoint slots are allocated by the first forward pass and reused
+        if t not in self.ckpt:
+            self.ckpt[t] = torch.empty_like(state)
+        self.ckpt[t].copy_(state)
+
     def _mom_slot(self, t):
         return self.kept[t - self.first_kept] if t >= self.first_kept else None
 
@@ -137,13 +147,13 @@ class Rollout:
         self.amp = amp.detach().to(self.device, torch.float64).contiguous()
         abi.lbm_init_rt3(self.params, self.desc, self.amp, self.buf[0], self.ghost)
         cur = 0
-        self.ckpt = {0: self.buf[0].clone()}
         saves = set(checkpoint_steps(c.nsteps, self.keep, self.ckpt_every))
+        self._save(0, self.buf[0])
         for t in range(1, c.nsteps + 1):
             self._step(self.buf[cur], self.buf[1 - cur], self._mom_slot(t))
             cur = 1 - cur
             if t in saves:
-                self.ckpt[t] = self.buf[cur].clone()
+                self._save(t, self.buf[cur])
         self.final = self.buf[cur]
         self.j = torch.empty(5, dtype=torch.float64, device=self.device)
         self.lam = [torch.empty((abi.Q, c.lx, c.lz), dtype=self.ldtype, device=self.device)

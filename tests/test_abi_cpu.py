@@ -206,3 +206,54 @@ def test_binding_constants_match_the_header():
         assert h["LBM_" + name] == getattr(mod, name), name
     status = {v: k for k, v in h.items() if k in ("LBM_OK",) or (k.startswith("LBM_E") and v < 0)}
     assert status == mod.STATUS
+
+
+def test_binding_rejects_mismatched_buffers():
+    """The binding checks each tensor's element type and size against the
+    parameters before the library sees its address: a float32 state with
+    FP64 parameters, float moments without LBM_MOM_F32, a short buffer or a
+    double adjoint buffer with LBM_ADJ_F32 raise ValueError (no launch; CPU
+    tensors suffice because the check comes first)."""
+    import torch
+
+    from paper_1405_1253_amd import abi as A
+    lx, lz = 4, 9
+    p64 = A.make_params(lx, lz, 0.7, 1e-4)
+    p32 = A.make_params(lx, lz, 0.7, 1e-4, A.F32_DEV)
+    st64 = torch.zeros((37, lx, lz), dtype=torch.float64)
+    st32 = torch.zeros((37, lx, lz), dtype=torch.float32)
+    gh64 = torch.zeros((2, 3, 37), dtype=torch.float64)
+    gh32 = torch.zeros((2, 3, 37), dtype=torch.float32)
+    mom64 = torch.zeros((4, lx, lz), dtype=torch.float64)
+    mom32 = torch.zeros((4, lx, lz), dtype=torch.float32)
+    cases = [
+        lambda: A.lbm_step(p64, gh64, st32, st64),                     # float state, FP64 params
+        lambda: A.lbm_step(p32, gh32, st32, st64),                     # double output, FP32 params
+        lambda: A.lbm_step(p64, gh32, st64, st64.clone()),             # float wall table
+        lambda: A.lbm_step(p64, gh64, st64, st64.clone(), mom32),      # float moments, no MOM_F32
+        lambda: A.lbm_step(A.make_params(lx, lz, 0.7, 1e-4, flags=A.MOM_F32), gh64, st64, st64.clone(), mom64),
+        lambda: A.lbm_step(p64, gh64, st64[:, :, :8].contiguous(), st64.clone()),   # too short
+        lambda: A.lbm_step_inplace(p64, gh64, st32, A.INPLACE_FROM_STATE),
+        lambda: A.lbm_moments(p64, st64, fields=mom32),
+        lambda: A.lbm_moments(p64, st64, tbar=torch.zeros(lz - 1, dtype=torch.float64)),
+        lambda: A.lbm_moments(p64, st64, sums=torch.zeros(3, dtype=torch.float64)),
+        lambda: A.lbm_adjoint_step(A.make_params(lx, lz, 0.7, 1e-4, flags=A.ADJ_F32), gh64, mom64, st64,
+                                   st64.clone()),                       # double lam with ADJ_F32
+        lambda: A.lbm_adjoint_step(p64, gh64, mom64, st32, st32.clone()),
+        lambda: A.lbm_adjoint_step(p64, gh64, mom64[:3].contiguous(), st64, st64.clone()),
+        lambda: A.lbm_profiles(p64, st64, torch.zeros((4, lz - 1), dtype=torch.float64), None),
+        lambda: A.lbm_objective(p64, A.RT3Desc(1.05, 1.0, 0.95, 4.0), st64, 1.0, 1.0,
+                                torch.zeros(4, dtype=torch.float64)),
+        lambda: A.lbm_init_rt3(p64, A.RT3Desc(1.05, 1.0, 0.95, 4.0, np.ones((2, 3)), np.zeros((2, 3))),
+                               torch.zeros((2, 3), dtype=torch.float32), st64, gh64),
+        lambda: A.lbm_init_rt3(p32, A.RT3Desc(1.05, 1.0, 0.95, 4.0), None, st64, gh32),
+        lambda: A.lbm_init_rt3_vjp(p64, A.RT3Desc(1.05, 1.0, 0.95, 4.0, np.ones((2, 3)), np.zeros((2, 3))),
+                                   torch.zeros((2, 3), dtype=torch.float64), st64,
+                                   torch.zeros((2, 2), dtype=torch.float64), None),
+    ]
+    for i, call in enumerate(cases):
+        with pytest.raises(ValueError):
+            call()
+    # matching buffers pass the check and reach the GPU-tensor check instead
+    with pytest.raises(ValueError, match="GPU tensors"):
+        A.lbm_step(p64, gh64, st64, st64.clone(), mom64)

@@ -7,7 +7,7 @@ Bars:
   contraction, the kernel as a factored polynomial: only rounding differs);
 * FP32 deviation storage against the FP64 oracle: the error bound derived in
   the FP32 tests below.
-Sizes span several 256-row tiles, a ragged tail and lattices smaller than the
+Sizes span ragged tails and lattices smaller than the
 velocity reach.
 """
 import numpy as np

@@ -42,9 +42,18 @@ def test_backward_plan(n, keep, c):
 def test_checkpoints_with_the_kept_interval():
     """Interval = kept steps (ckpt_every = 0 in RolloutConfig): 5000 steps,
     1237 kept -> 3763 steps to recompute in 4 segments from the states after
-    0, 1237, 2474 and 3711 (16 states with an interval of 250)."""
-    assert checkpoint_steps(5000, 1237, 1237) == [0, 1237, 2474, 3711]
-    assert len(checkpoint_steps(5000, 1237, 250)) == 16
+    0, 1237, 2474 and 3711; the state after 4948 is stored as well (20
+    states with an interval of 250)."""
+    assert checkpoint_steps(5000, 1237, 1237) == [0, 1237, 2474, 3711, 4948]
+    assert len(checkpoint_steps(5000, 1237, 250)) == 20
     plan = backward_plan(5000, 1237, 1237)
     assert [op[1:] for op in plan if op[0] == "recompute"] == [(3711, 3763), (2474, 3711), (1237, 2474),
                                                                (0, 1237)]
+
+
+def test_checkpoints_every_interval_when_all_moments_are_kept():
+    """A 2000-step rollout with a checkpoint every 100 steps stores the states
+    after 0, 100, ..., 1900 even when every step's moments are kept (and the
+    backward sweep then recomputes nothing)."""
+    assert checkpoint_steps(2000, 2000, 100) == list(range(0, 2000, 100))
+    assert [op for op in backward_plan(2000, 2000, 100) if op[0] == "recompute"] == []
