@@ -123,3 +123,40 @@ def test_profiles_closed_forms():
     assert np.allclose(prof[1], eps * np.abs(s) / np.sqrt(2), atol=1e-14)
     assert np.allclose(prof[2], rho0 * a * a / 4, rtol=1e-12)
     assert np.allclose(prof[3], rho0 * a * a / (4 * np.sqrt(2)), rtol=1e-12)
+
+
+def test_renormalised_fields_are_the_mid_step_average():
+    """hydro_fields, pinned without the init: Sec. III.A's renormalised
+    velocity and temperature are the averages over the collision of the
+    pre- and post-collision momentum and energy.  From an arbitrary
+    (non-equilibrium) pre-collision state, one oracle collide (pinned by the
+    collide identities) gives the stored state; the plain sums
+    sum xi f and sum |xi|^2 f / 2 before and after, averaged, must give
+    u^H = <rho u> / rho and T^H = (<E> / rho - |u^H|^2) / D -- i.e. u^H =
+    u* - g_vec/2 and T^H = T* + g^2/8 with g_vec = (0, -g).  A large g
+    (0.05) makes g^2/8 = 3e-4: a sign error in either shift, or a shift by
+    g_vec or g^2/4, fails by orders of magnitude more than the tolerance."""
+    _, xi, w, _ = L.lattice()
+    rng = np.random.default_rng(8)
+    lx, lz, g = 3, 5, 0.05
+    p = lbm.Params(lx, lz, 0.8, g)
+    pre = w[:, None, None] * rng.uniform(0.6, 1.4, (37, lx, lz))
+    post = lbm.collide(pre, p)
+
+    def sums(f):
+        return (f.sum(axis=0), np.tensordot(xi.T, f, axes=(1, 0)),
+                0.5 * np.tensordot((xi ** 2).sum(axis=1), f, axes=(0, 0)))
+
+    rho0, j0, e0 = sums(pre)
+    rho1, j1, e1 = sums(post)
+    assert np.allclose(rho0, rho1, rtol=0, atol=1e-15)
+    uH = 0.5 * (j0 + j1) / rho0                                        # [2, lx, lz]
+    TH = (0.5 * (e0 + e1) * 2 / rho0 - (uH ** 2).sum(axis=0)) / 2       # D = 2, E = sum |xi|^2 f / 2
+    rho, uH_o, TH_o = lbm.hydro_fields(post, p)
+    assert np.allclose(rho, rho0, rtol=1e-15, atol=0)
+    assert np.abs(np.moveaxis(uH_o, -1, 0) - uH).max() <= 1e-13
+    assert np.abs(TH_o - TH).max() <= 1e-13
+    # the wrong-sign readings sit far outside that tolerance
+    _, ustar, Tstar = lbm.moments(post)
+    assert np.abs(Tstar - g ** 2 / 8 - TH).min() >= 5e-4
+    assert np.abs(ustar[..., 1] - g / 2 - uH[1]).min() >= 0.04
