@@ -44,7 +44,9 @@
  *
  * Memory and streams.  Pointers marked (device) are device memory, (host)
  * host memory.  All buffers are owned by the caller; the library allocates,
- * frees and synchronises nothing, and keeps no mutable global state.  Every
+ * frees and synchronises nothing (device or host memory), and keeps no
+ * mutable global state other than lbm_moments_noalloc's per-device scratch
+ * array and the per-thread text of the last HIP error.  Every
  * call only enqueues work on `stream` (a hipStream_t; NULL = null stream) and
  * returns; results are ready when the stream reaches that point.
  *
@@ -76,7 +78,9 @@ enum lbm_status {
     LBM_EALIGN = -3,     /* a device pointer is not 16-byte aligned                    */
     LBM_EHIP = -4,       /* the HIP runtime refused a launch; see lbm_last_hip_error   */
     LBM_ESCRATCH = -5,   /* scratch buffer missing or smaller than lbm_scratch_bytes   */
-    LBM_EVERSION = -6    /* params->abi_version != LBM_ABI_VERSION                      */
+    LBM_EVERSION = -6,   /* params->abi_version != LBM_ABI_VERSION                      */
+    LBM_ESTATIC = -7     /* the lattice needs more than LBM_STATIC_SCRATCH_BYTES of
+                            scratch (lbm_moments_noalloc only)                       */
 };
 
 enum lbm_precision { LBM_F64 = 0, LBM_F32_DEV = 1 };
@@ -239,6 +243,32 @@ size_t lbm_scratch_bytes(const lbm_params *params);
  */
 int lbm_moments(const lbm_params *params, const void *f, double *fields, double *tbar,
                 double *sums, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+
+/*
+ * lbm_moments_noalloc -- lbm_moments without a caller-supplied scratch buffer.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * kernels, results (bit for bit) and errors as lbm_moments, but the
+ * partial sums go to a device array that the library holds, one per GPU it
+ * runs on, of LBM_STATIC_SCRATCH_BYTES bytes (kept until the process ends;
+ * its address is looked up on the first call on each device).  The call
+ * allocates nothing, host or device.  The array needs no clearing: every
+ * word a call reads was written earlier by the same call.  All calls on one
+ * GPU share the array, so calls that overlap in time on one GPU (different
+ * streams, or different host threads without ordering) race and give wrong
+ * tbar/sums; serialise them, e.g. on one stream.
+ *
+ *   f, fields, tbar, sums  as for lbm_moments
+ * Scratch is needed only for tbar or sums: about 8 ceil(Lx/64) Lz bytes
+ * (e.g. 6.4 MB at 4096 x 12288).
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP,
+ * LBM_ESTATIC (tbar or sums requested on a lattice whose scratch would exceed
+ * LBM_STATIC_SCRATCH_BYTES).
+ */
+#define LBM_STATIC_SCRATCH_BYTES (16u << 20)
+int lbm_moments_noalloc(const lbm_params *params, const void *f, double *fields, double *tbar,
+                        double *sums, lbm_stream_t stream);
 
 /*
  * lbm_profiles -- horizontal mean and rms fluctuation profiles of a state.

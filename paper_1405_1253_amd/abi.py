@@ -24,7 +24,8 @@ PERIODIC_Z, NO_COLLIDE, ADJ_F32, WALL_DIFFUSE, MOM_F32 = 1, 2, 4, 8, 16
 INPLACE_FROM_STATE, INPLACE_FROM_STREAMED = 0, 1
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EALIAS", -3: "LBM_EALIGN",
-          -4: "LBM_EHIP", -5: "LBM_ESCRATCH", -6: "LBM_EVERSION"}
+          -4: "LBM_EHIP", -5: "LBM_ESCRATCH", -6: "LBM_EVERSION", -7: "LBM_ESTATIC"}
+STATIC_SCRATCH_BYTES = 16 << 20
 
 
 class LbmError(RuntimeError):
@@ -72,6 +73,7 @@ def load():
         lib.lbm_step_inplace.argtypes = [P(lbm_params), _VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_size_t,
                                          _VP]
         lib.lbm_moments.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+        lib.lbm_moments_noalloc.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
         lib.lbm_scratch_bytes.argtypes = [P(lbm_params)]
         lib.lbm_scratch_bytes.restype = ctypes.c_size_t
         lib.lbm_lattice.argtypes = [P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
@@ -85,7 +87,8 @@ def load():
         lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP]
         lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
-        for name in ("lbm_init_rt3", "lbm_step", "lbm_step_inplace", "lbm_moments", "lbm_lattice", "lbm_objective",
+        for name in ("lbm_init_rt3", "lbm_step", "lbm_step_inplace", "lbm_moments", "lbm_moments_noalloc",
+                     "lbm_lattice", "lbm_objective",
                      "lbm_adjoint_step", "lbm_init_rt3_vjp", "lbm_profiles"):
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
@@ -235,6 +238,18 @@ def lbm_moments(params, f, fields=None, tbar=None, sums=None, scratch=None, stre
     st = load().lbm_moments(ctypes.byref(params), _ptr(f), _ptr(fields), _ptr(tbar), _ptr(sums),
                             _ptr(scratch), nbytes, _stream(stream))
     _check(st, "lbm_moments")
+
+
+def lbm_moments_noalloc(params, f, fields=None, tbar=None, sums=None, stream=None):
+    """lbm_moments with the library's own static scratch: no allocation
+    (see include/lbm.h; calls overlapping on one GPU race)."""
+    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("fields", fields, _f64(), 4 * _sites(params))
+    _need("tbar", tbar, _f64(), int(params.lz))
+    _need("sums", sums, _f64(), 4)
+    st = load().lbm_moments_noalloc(ctypes.byref(params), _ptr(f), _ptr(fields), _ptr(tbar), _ptr(sums),
+                                    _stream(stream))
+    _check(st, "lbm_moments_noalloc")
 
 
 def lbm_lattice():

@@ -5,9 +5,14 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "../../include/lbm.h"
 #include "common.h"
 #include "kernels.h"
+
+// Scratch of the allocation-free diagnostics entry point (lbm_moments_noalloc).
+static __device__ __align__(256) unsigned char scratch[LBM_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -118,6 +123,31 @@ int check_desc(const lbm_rt3_desc *d, const double *amp) {
     return LBM_OK;
 }
 
+// The allocation-free diagnostics entry point's scratch: one array per device
+// (each GPU the library runs on holds its own copy until the process ends).
+// Host code never uses the array's name as an address: its device address is
+// looked up once per device and kept in g_static_scratch.
+constexpr int MAX_DEVICES = 64;
+std::atomic<void *> g_static_scratch[MAX_DEVICES];
+
+// Device address of the current device's array (looked up on the first call
+// on that device; concurrent first calls store the same address).
+int static_scratch(void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return LBM_EINVAL;
+    void *p = g_static_scratch[dev].load(std::memory_order_acquire);
+    if (!p) {
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e);
+        if (!p) return LBM_EHIP;
+        g_static_scratch[dev].store(p, std::memory_order_release);
+    }
+    *ptr = p;
+    return LBM_OK;
+}
+
 size_t lam_bytes(const lbm_params *p) {
     return (size_t)LBM_Q * p->lx * p->lz * ((p->flags & LBM_ADJ_F32) ? sizeof(float) : sizeof(double));
 }
@@ -136,6 +166,7 @@ const char *lbm_strerror(int status) {
         case LBM_EHIP: return "HIP runtime error";
         case LBM_ESCRATCH: return "scratch buffer missing or too small";
         case LBM_EVERSION: return "lbm_params.abi_version does not match the library";
+        case LBM_ESTATIC: return "lattice too large for the library's static scratch array";
         default: return "unknown status";
     }
 }
@@ -279,6 +310,36 @@ int lbm_moments(const lbm_params *p, const void *f, double *fields, double *tbar
     a.tbar = tbar;
     a.sums = sums;
     a.scratch = scratch;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.g = p->g;
+    return hip_status(lbm::launch_moments(a, p->precision, (hipStream_t)stream));
+}
+
+int lbm_moments_noalloc(const lbm_params *p, const void *f, double *fields, double *tbar, double *sums,
+                        lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!f) return LBM_EINVAL;
+    if (!aligned(f, 16) || !aligned(fields, 8) || !aligned(tbar, 8) || !aligned(sums, 8)) return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const bool need_scratch = tbar || sums;
+    const size_t need = need_scratch ? lbm::moments_scratch_bytes(p->lx, p->lz) : 0;
+    if (need > (size_t)LBM_STATIC_SCRATCH_BYTES) return LBM_ESTATIC;
+    const size_t sb = state_bytes(p), fb = field_bytes(p), tb = (size_t)p->lz * sizeof(double);
+    if (overlap(fields, fb, f, sb) || overlap(tbar, tb, f, sb) || overlap(sums, 32, f, sb) ||
+        overlap(fields, fb, tbar, tb) || overlap(fields, fb, sums, 32) || overlap(tbar, tb, sums, 32))
+        return LBM_EALIAS;
+    if (!fields && !tbar && !sums) return LBM_OK;
+    void *scr = nullptr;
+    if (need_scratch && (st = static_scratch(&scr)) != LBM_OK) return st;
+    lbm::MomentArgs a;
+    a.f = f;
+    a.fields = fields;
+    a.tbar = tbar;
+    a.sums = sums;
+    a.scratch = scr;
     a.lx = p->lx;
     a.lz = p->lz;
     a.g = p->g;
