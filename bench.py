@@ -294,7 +294,7 @@ def propagate_pull_vs_push(wl, launches=20, rounds=2):
         p_pull = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, pr, abi.NO_COLLIDE)
         p_push = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, pr, abi.NO_COLLIDE | (abi.ADJ_F32 if f32 else 0))
         dt = torch.float32 if f32 else torch.float64
-        buf = [torch.rand((abi.Q, wl.lx, wl.lz), dtype=dt, device="cuda") for _ in range(2)]
+        buf = [torch.rand(abi.population_elems(p_pull), dtype=dt, device="cuda") for _ in range(2)]
         gh = torch.rand((2, 3, abi.Q), dtype=dt, device="cuda")
 
         def timed(fn):
@@ -349,7 +349,7 @@ def adjoint_counter_run(launches=6):
     p_fwd = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, base, abi.MOM_F32)
     p_adj = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, base, abi.MOM_F32 | abi.ADJ_F32)
     p_str = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, base, abi.NO_COLLIDE | abi.ADJ_F32)
-    shape = (abi.Q, wl.lx, wl.lz)
+    shape = (abi.population_elems(p_fwd),)
     f = torch.empty(shape, dtype=torch.float32, device="cuda")
     gh = torch.empty((2, 3, abi.Q), dtype=torch.float32, device="cuda")
     abi.lbm_init_rt3(p_fwd, abi.RT3Desc(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase),

@@ -25,12 +25,21 @@
  *    l = 29..36       (3,1) (-3,-1) (3,-1) (-3,1) (1,3) (-1,-3) (1,-3) (-1,3)
  * i.e. the rest velocity, then shell by shell, each +e followed by -e.
  *
- * Layout.  A population buffer is structure-of-arrays [37][Lx][Lz], z
- * fastest (Sec. III.B).  Element type by precision:
+ * Layout.  A population buffer (the state, and the adjoint buffers) is
+ * tiled: rows are grouped in tiles of LBM_TILE = 512, and tile zt of column
+ * x holds its 37 populations as 37 consecutive runs of LBM_TILE rows,
+ *     element (l, x, z) at index ((zt Lx + x) 37 + l) LBM_TILE + (z - zt LBM_TILE),
+ *     zt = floor(z / LBM_TILE),
+ * i.e. the structure-of-arrays layout of Sec. III.B applied per tile.  A
+ * buffer holds lbm_population_elems(params) = 37 Lx ceil(Lz / 512) 512
+ * elements; the rows from Lz up to the next multiple of 512 are padding,
+ * which no entry point reads.  lbm_pack and lbm_unpack convert from and to
+ * the plain layout [37][Lx][Lz] (z fastest).  Element type by precision:
  *    LBM_F64      double, the population f_l itself;
  *    LBM_F32_DEV  float, the deviation f_l - w_l from the rest state of unit
  *                 density (w_l = quadrature weight).
- * Field buffers ([4][Lx][Lz], [Lz]) are always double.
+ * Field buffers ([4][Lx][Lz], [Lz]) are always double, in the plain layout;
+ * so are the step's moments ([4][Lx][Lz]).
  *
  * State.  Buffers hold post-collision populations f*.  A step reads one
  * buffer and writes the other (the paper's prv/nxt pair, Sec. III.B).
@@ -65,9 +74,10 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3u
+#define LBM_ABI_VERSION 4u
 #define LBM_Q 37
 #define LBM_MAX_MODES 32 /* interface modes per front accepted by lbm_init_rt3 */
+#define LBM_TILE 512     /* rows per tile of a population buffer (see Layout)   */
 
 typedef void *lbm_stream_t; /* hipStream_t */
 
@@ -141,7 +151,7 @@ typedef struct lbm_rt3_desc {
  * each wall.
  *
  *   amp        (device) double [2][desc->nmodes]
- *   f_out      (device) state buffer [37][Lx][Lz], written
+ *   f_out      (device) state buffer (tiled), written
  *   ghost_out  (device) wall table [2][3][37], written
  * Errors: LBM_EINVAL (sizes, nmodes, width <= 0, NULL), LBM_EALIAS (f_out and
  * ghost_out overlap), LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
@@ -215,6 +225,29 @@ int lbm_step(const lbm_params *params, const void *ghost, const void *f_in, void
 enum lbm_inplace_kind { LBM_INPLACE_FROM_STATE = 0, LBM_INPLACE_FROM_STREAMED = 1 };
 int lbm_step_inplace(const lbm_params *params, const void *ghost, void *f, int kind,
                      double *moments_out, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+
+/*
+ * lbm_population_elems -- number of elements of a population buffer (the
+ * state, lam buffers) in the tiled layout: 37 Lx ceil(Lz / LBM_TILE)
+ * LBM_TILE.  Returns 0 for invalid params.
+ */
+size_t lbm_population_elems(const lbm_params *params);
+
+/*
+ * lbm_pack, lbm_unpack -- convert a population buffer between the plain
+ * layout [37][Lx][Lz] (z fastest) and the library's tiled layout.  A pure
+ * permutation of elements of elt_bytes = 4 or 8 bytes (float or double
+ * buffers of either precision): bit-exact both ways.  lbm_pack writes every
+ * element of the tiled buffer, the padding rows as zero bits.
+ *
+ *   soa    (device) [37][Lx][Lz] elements
+ *   tiled  (device) lbm_population_elems(params) elements
+ * The two buffers must not overlap.
+ * Errors: LBM_EINVAL (elt_bytes, NULL), LBM_EALIAS, LBM_EALIGN (a pointer not
+ * aligned to elt_bytes), LBM_EVERSION, LBM_EHIP.
+ */
+int lbm_pack(const lbm_params *params, const void *soa, void *tiled, int elt_bytes, lbm_stream_t stream);
+int lbm_unpack(const lbm_params *params, const void *tiled, void *soa, int elt_bytes, lbm_stream_t stream);
 
 /*
  * lbm_scratch_bytes -- size of the scratch buffer that lbm_moments,
@@ -300,7 +333,7 @@ int lbm_profiles(const lbm_params *params, const void *f, double *prof, void *sc
  *   desc      (host) only t_d > t_m > t_u are used
  *   f         (device) state buffer
  *   j_out     (device) double [5]: J, KE, L_u + L_d, L_u, L_d
- *   lam_seed  (device, nullable) [37][Lx][Lz] (double, or float with LBM_ADJ_F32):
+ *   lam_seed  (device, nullable) population buffer (double, or float with LBM_ADJ_F32):
  *             dJ/df_l at every site
  *             (the tent map's slope is taken as 2, -2, 0 on the three pieces)
  *   scratch   (device) at least lbm_scratch_bytes(params) bytes
@@ -331,7 +364,7 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  *   moments  (device) double [4][Lx][Lz] (float with LBM_MOM_F32): rho, u_x,
  *            u_z, T written by the forward lbm_step's moments_out (may be NULL
  *            with LBM_NO_COLLIDE)
- *   lam_in   (device) [37][Lx][Lz], double (float with LBM_ADJ_F32)
+ *   lam_in   (device) population buffer, double (float with LBM_ADJ_F32)
  *   lam_out  (device) same type and shape, must not overlap lam_in, moments
  *            or ghost
  * The adjoint arithmetic is double, except with both LBM_ADJ_F32 and
@@ -353,7 +386,7 @@ int lbm_adjoint_step(const lbm_params *params, const void *ghost, const double *
  * equilibrium (Sec. I, eq. seteq).  The wall table does not depend on amp.
  *
  *   desc, amp  as passed to lbm_init_rt3
- *   lam0       (device) [37][Lx][Lz] (double, or float with LBM_ADJ_F32): dJ/df*_0
+ *   lam0       (device) population buffer (double, or float with LBM_ADJ_F32): dJ/df*_0
  *   d_amp      (device) double [2][nmodes], written
  *   scratch    (device) at least lbm_scratch_bytes(params) bytes
  * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION, LBM_EHIP.

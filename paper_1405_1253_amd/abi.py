@@ -1,7 +1,9 @@
 """ctypes binding of liblbm.so: the C entry points under the same names.
 
 Argument marshalling only -- every step of the method runs in the library's
-HIP kernels.  Before a call, each tensor's element type and size are checked
+HIP kernels.  Population buffers (the state, adjoint buffers) are in the
+library's tiled layout (include/lbm.h); to_tiled / to_soa convert to and from
+the plain [37, Lx, Lz] layout through the library's pack/unpack kernels.  Before a call, each tensor's element type and size are checked
 against what the parameters imply (the C entry points see only addresses),
 so a mismatched buffer raises ValueError instead of being overrun.  Buffers are torch tensors (device memory) or raw integer
 addresses; streams default to torch's current stream.  A failing call raises
@@ -16,9 +18,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 Q = 37
 MAX_MODES = 32
+TILE = 512   # rows per tile of a population buffer (tiled layout, include/lbm.h)
 F64, F32_DEV = 0, 1
 PERIODIC_Z, NO_COLLIDE, ADJ_F32, WALL_DIFFUSE, MOM_F32 = 1, 2, 4, 8, 16
 INPLACE_FROM_STATE, INPLACE_FROM_STREAMED = 0, 1
@@ -74,6 +77,10 @@ def load():
                                          _VP]
         lib.lbm_moments.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
         lib.lbm_moments_noalloc.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
+        lib.lbm_population_elems.argtypes = [P(lbm_params)]
+        lib.lbm_population_elems.restype = ctypes.c_size_t
+        lib.lbm_pack.argtypes = [P(lbm_params), _VP, _VP, ctypes.c_int, _VP]
+        lib.lbm_unpack.argtypes = [P(lbm_params), _VP, _VP, ctypes.c_int, _VP]
         lib.lbm_scratch_bytes.argtypes = [P(lbm_params)]
         lib.lbm_scratch_bytes.restype = ctypes.c_size_t
         lib.lbm_lattice.argtypes = [P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_int32)]
@@ -88,7 +95,7 @@ def load():
                                          ctypes.c_size_t, _VP]
         lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
         for name in ("lbm_init_rt3", "lbm_step", "lbm_step_inplace", "lbm_moments", "lbm_moments_noalloc",
-                     "lbm_lattice", "lbm_objective",
+                     "lbm_lattice", "lbm_objective", "lbm_pack", "lbm_unpack",
                      "lbm_adjoint_step", "lbm_init_rt3_vjp", "lbm_profiles"):
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
@@ -121,6 +128,12 @@ def _ptr(x):
 
 def _sites(params):
     return int(params.lx) * int(params.lz)
+
+
+def population_elems(params):
+    """Elements of a population buffer (state or adjoint) in the tiled
+    layout: 37 Lx ceil(Lz / TILE) TILE (the same as lbm_population_elems)."""
+    return Q * int(params.lx) * (-(-int(params.lz) // TILE)) * TILE
 
 
 def _state_dtype(params):
@@ -195,7 +208,7 @@ def lbm_init_rt3(params, desc, amp, f_out, ghost_out, stream=None):
 
     desc: RT3Desc (host k, phase [2, nmodes]); amp: device float64 [2, nmodes]."""
     _need("amp", amp, _f64(), 2 * desc.nmodes)
-    _need("f_out", f_out, _state_dtype(params), Q * _sites(params))
+    _need("f_out", f_out, _state_dtype(params), population_elems(params))
     _need("ghost_out", ghost_out, _state_dtype(params), 2 * 3 * Q)
     st = load().lbm_init_rt3(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(f_out),
                              _ptr(ghost_out), _stream(stream))
@@ -205,8 +218,8 @@ def lbm_init_rt3(params, desc, amp, f_out, ghost_out, stream=None):
 def lbm_step(params, ghost, f_in, f_out, moments_out=None, stream=None):
     """One fused propagate + bc + collide step (see include/lbm.h)."""
     _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
-    _need("f_in", f_in, _state_dtype(params), Q * _sites(params))
-    _need("f_out", f_out, _state_dtype(params), Q * _sites(params))
+    _need("f_in", f_in, _state_dtype(params), population_elems(params))
+    _need("f_out", f_out, _state_dtype(params), population_elems(params))
     _need("moments_out", moments_out, _mom_dtype(params), 4 * _sites(params))
     st = load().lbm_step(ctypes.byref(params), _ptr(ghost), _ptr(f_in), _ptr(f_out),
                          _ptr(moments_out), _stream(stream))
@@ -217,7 +230,7 @@ def lbm_step_inplace(params, ghost, f, kind, moments_out=None, scratch=None, str
     """One step on a single buffer, kind INPLACE_FROM_STATE or
     INPLACE_FROM_STREAMED (see include/lbm.h)."""
     _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
-    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("f", f, _state_dtype(params), population_elems(params))
     _need("moments_out", moments_out, _mom_dtype(params), 4 * _sites(params))
     st = load().lbm_step_inplace(ctypes.byref(params), _ptr(ghost), _ptr(f), int(kind), _ptr(moments_out),
                                  _ptr(scratch), _nbytes(scratch), _stream(stream))
@@ -230,7 +243,7 @@ def lbm_scratch_bytes(params):
 
 def lbm_moments(params, f, fields=None, tbar=None, sums=None, scratch=None, stream=None):
     """Renormalised fields, mean profile and global sums (see include/lbm.h)."""
-    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("f", f, _state_dtype(params), population_elems(params))
     _need("fields", fields, _f64(), 4 * _sites(params))
     _need("tbar", tbar, _f64(), int(params.lz))
     _need("sums", sums, _f64(), 4)
@@ -243,13 +256,79 @@ def lbm_moments(params, f, fields=None, tbar=None, sums=None, scratch=None, stre
 def lbm_moments_noalloc(params, f, fields=None, tbar=None, sums=None, stream=None):
     """lbm_moments with the library's own static scratch: no allocation
     (see include/lbm.h; calls overlapping on one GPU race)."""
-    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("f", f, _state_dtype(params), population_elems(params))
     _need("fields", fields, _f64(), 4 * _sites(params))
     _need("tbar", tbar, _f64(), int(params.lz))
     _need("sums", sums, _f64(), 4)
     st = load().lbm_moments_noalloc(ctypes.byref(params), _ptr(f), _ptr(fields), _ptr(tbar), _ptr(sums),
                                     _stream(stream))
     _check(st, "lbm_moments_noalloc")
+
+
+def _elt(x):
+    return x.element_size() if not isinstance(x, int) else None
+
+
+def lbm_pack(params, soa, tiled, elt_bytes=None, stream=None):
+    """Plain [37][Lx][Lz] buffer -> tiled population buffer (see include/lbm.h)."""
+    elt = elt_bytes or _elt(soa)
+    for name, t, n in (("soa", soa, Q * _sites(params)), ("tiled", tiled, population_elems(params))):
+        if not isinstance(t, int):
+            if t.element_size() != elt:
+                raise ValueError(f"{name}: element size {t.element_size()}, expected {elt}")
+            if t.numel() < n:
+                raise ValueError(f"{name}: {t.numel()} elements, expected at least {n}")
+    st = load().lbm_pack(ctypes.byref(params), _ptr(soa), _ptr(tiled), int(elt), _stream(stream))
+    _check(st, "lbm_pack")
+
+
+def lbm_unpack(params, tiled, soa, elt_bytes=None, stream=None):
+    """Tiled population buffer -> plain [37][Lx][Lz] buffer (see include/lbm.h)."""
+    elt = elt_bytes or _elt(tiled)
+    for name, t, n in (("tiled", tiled, population_elems(params)), ("soa", soa, Q * _sites(params))):
+        if not isinstance(t, int):
+            if t.element_size() != elt:
+                raise ValueError(f"{name}: element size {t.element_size()}, expected {elt}")
+            if t.numel() < n:
+                raise ValueError(f"{name}: {t.numel()} elements, expected at least {n}")
+    st = load().lbm_unpack(ctypes.byref(params), _ptr(tiled), _ptr(soa), int(elt), _stream(stream))
+    _check(st, "lbm_unpack")
+
+
+def empty_populations(params, dtype, device="cuda"):
+    """An uninitialised population buffer (tiled layout) of element type dtype."""
+    import torch
+    return torch.empty(population_elems(params), dtype=dtype, device=device)
+
+
+def to_tiled(params, soa, device="cuda"):
+    """A new tiled buffer holding the plain-layout populations `soa` ([37, Lx,
+    Lz] numpy array or tensor; the element type is kept)."""
+    import torch
+    src = torch.as_tensor(soa).to(device).contiguous()
+    out = empty_populations(params, src.dtype, device)
+    lbm_pack(params, src, out)
+    return out
+
+
+def to_soa(params, tiled):
+    """A new [37, Lx, Lz] tensor (same device and element type) holding the
+    populations of the tiled buffer."""
+    import torch
+    out = torch.empty((Q, int(params.lx), int(params.lz)), dtype=tiled.dtype, device=tiled.device)
+    lbm_unpack(params, tiled, out)
+    return out
+
+
+def tiled_view(params, t):
+    """A [ceil(Lz / TILE), Lx, 37, TILE] view of a tiled population buffer."""
+    return t.view(-(-int(params.lz) // TILE), int(params.lx), Q, TILE)
+
+
+def column(params, t, x):
+    """The populations of column x of a tiled buffer as a new [37, Lz] tensor."""
+    v = tiled_view(params, t)[:, x]                       # [tiles, 37, TILE]
+    return v.permute(1, 0, 2).reshape(Q, -1)[:, :int(params.lz)].contiguous()
 
 
 def lbm_lattice():
@@ -268,9 +347,9 @@ def _nbytes(t):
 def lbm_objective(params, desc, f, wk, wl, j_out, lam_seed=None, scratch=None, stream=None):
     """J = wk KE + wl (L_u + L_d) into j_out[5] = (J, KE, L_u + L_d, L_u, L_d) and
     optionally dJ/df (see include/lbm.h)."""
-    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("f", f, _state_dtype(params), population_elems(params))
     _need("j_out", j_out, _f64(), 5)
-    _need("lam_seed", lam_seed, _lam_dtype(params), Q * _sites(params))
+    _need("lam_seed", lam_seed, _lam_dtype(params), population_elems(params))
     st = load().lbm_objective(ctypes.byref(params), ctypes.byref(desc.c), _ptr(f), wk, wl,
                               _ptr(j_out), _ptr(lam_seed), _ptr(scratch), _nbytes(scratch),
                               _stream(stream))
@@ -282,8 +361,8 @@ def lbm_adjoint_step(params, ghost, moments, lam_in, lam_out, stream=None):
     the forward step's wall table (needed with WALL_DIFFUSE, else may be None)."""
     _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
     _need("moments", moments, _mom_dtype(params), 4 * _sites(params))
-    _need("lam_in", lam_in, _lam_dtype(params), Q * _sites(params))
-    _need("lam_out", lam_out, _lam_dtype(params), Q * _sites(params))
+    _need("lam_in", lam_in, _lam_dtype(params), population_elems(params))
+    _need("lam_out", lam_out, _lam_dtype(params), population_elems(params))
     st = load().lbm_adjoint_step(ctypes.byref(params), _ptr(ghost), _ptr(moments), _ptr(lam_in),
                                  _ptr(lam_out), _stream(stream))
     _check(st, "lbm_adjoint_step")
@@ -292,7 +371,7 @@ def lbm_adjoint_step(params, ghost, moments, lam_in, lam_out, stream=None):
 def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):
     """d_amp = (d init / d amp)^T lam0 (see include/lbm.h)."""
     _need("amp", amp, _f64(), 2 * desc.nmodes)
-    _need("lam0", lam0, _lam_dtype(params), Q * _sites(params))
+    _need("lam0", lam0, _lam_dtype(params), population_elems(params))
     _need("d_amp", d_amp, _f64(), 2 * desc.nmodes)
     st = load().lbm_init_rt3_vjp(ctypes.byref(params), ctypes.byref(desc.c), _ptr(amp), _ptr(lam0),
                                  _ptr(d_amp), _ptr(scratch), _nbytes(scratch), _stream(stream))
@@ -301,7 +380,7 @@ def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):
 
 def lbm_profiles(params, f, prof, scratch, stream=None):
     """Row means and rms fluctuations of T^H and E_k into prof [4, Lz] (see include/lbm.h)."""
-    _need("f", f, _state_dtype(params), Q * _sites(params))
+    _need("f", f, _state_dtype(params), population_elems(params))
     _need("prof", prof, _f64(), 4 * int(params.lz))
     st = load().lbm_profiles(ctypes.byref(params), _ptr(f), _ptr(prof), _ptr(scratch),
                              _nbytes(scratch), _stream(stream))

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["api.hip", "step.hip", "moments.hip", "init.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "step.hip", "moments.hip", "init.hip", "adjoint.hip", "layout.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

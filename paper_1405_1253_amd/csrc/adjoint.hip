@@ -13,7 +13,8 @@
 // and lam_{t-1,l}(y) = G_l(y + e_l).  Each site computes its own G from its
 // own 37 lam values and 4 moments and writes G_l to site x - e_l: every
 // output element has exactly one writer (a permutation), so the kernel moves
-// 37 + 4 reads and 37 writes per site.  Rows y whose source y + e_l lies
+// 37 + 4 reads and 37 writes per site.  The lam buffers use the tiled layout
+// of the state (common.h); the moments are [4][Lx][Lz].  Rows y whose source y + e_l lies
 // beyond a wall receive an explicit zero with the Dirichlet wall (those pulls
 // read the constant wall table, which carries no derivative).
 //
@@ -155,19 +156,21 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
                                         double>::type;
     const L *__restrict__ lam_in = static_cast<const L *>(a.lam_in);
     L *__restrict__ lam_out = static_cast<L *>(a.lam_out);
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;   // moments: [4][Lx][Lz]
     const int z = z0 + (int)threadIdx.x;
     if (EDGE && z >= a.lz) return;
-    const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
-    // uniform column base + 32-bit per-lane byte offset for every access
-    const uint32_t loff = (uint32_t)z * (uint32_t)sizeof(L);
+    // lam buffers are tiled (common.h); the block's rows lie in one tile zt
+    const int zt = z0 / TILE, zl = z % TILE;
+    const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
+    const size_t own = ((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)zl;   // (0, x, z)
     L lam[Q];   // held in the buffer's type (float buffers: half the registers)
 #pragma unroll
-    for (int l = 0; l < Q; ++l) lam[l] = ldg_off(lam_in + (size_t)l * N + (size_t)x * (size_t)a.lz, loff);
+    for (int l = 0; l < Q; ++l) lam[l] = lam_in[own + (size_t)l * TILE];
 
     // G_l = keep lam_l + alpha + beta . xi_l + gamma |xi_l|^2 (NO_COLLIDE: G = lam)
     double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
     if (!(a.flags & F_NO_COLLIDE)) {
+        // uniform column base + 32-bit per-lane byte offset
         const MT *mcol = static_cast<const MT *>(a.mom) + (size_t)x * (size_t)a.lz;
         const uint32_t moff = (uint32_t)z * (uint32_t)sizeof(MT);
         const double rho = ldg_off(mcol, moff), ux = ldg_off(mcol + N, moff),
@@ -209,13 +212,14 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
         const L G = (L)gval(l);
         const int xd = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
         const int zd = z - EZ[l];
-        L *dst = lam_out + (size_t)l * N + (size_t)xd * (size_t)a.lz;
         if (!EDGE) {
-            stg_off(dst - EZ[l], loff, G);
+            // row z - e_lz of column x - e_lx: this tile or the one below / above
+            L *tb = lam_out + ((size_t)zt * (size_t)a.lx + (size_t)xd) * (Q * TILE);
+            tb[tile_off(l, zl - EZ[l], tstep)] = G;
         } else if (a.flags & F_PERIODIC_Z) {
-            dst[wrap(zd, a.lz)] = G;
+            lam_out[pidx(l, xd, wrap(zd, a.lz), a.lx)] = G;
         } else {
-            if (zd >= 0 && zd < a.lz) dst[zd] = G;
+            if (zd >= 0 && zd < a.lz) lam_out[pidx(l, xd, zd, a.lx)] = G;
             // lam_out_l(z) = G_l(z + e_lz) has no writer when row z + e_lz lies
             // beyond a wall: zero for the Dirichlet wall (that pull read the
             // constant table); the diffuse wall parks G_{-l} of this site there
@@ -226,7 +230,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
                     const int o = l == 0 ? 0 : ((l & 1) ? l + 1 : l - 1);   // -e_l
                     park = (L)gval(o);
                 }
-                lam_out[(size_t)l * N + site] = park;
+                lam_out[own + (size_t)l * TILE] = park;
             }
         }
     }
@@ -239,6 +243,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
 #define LBM_ADJ_ZT 1
 #endif
 constexpr int ADJ_BS = LBM_ADJ_BS, ADJ_ZT = LBM_ADJ_ZT;
+static_assert(TILE % ADJ_BS == 0, "an adjoint block's rows must lie in one tile of the lam buffers");
 
 // L: element type of the adjoint buffers; MT: of the stored moments
 // Occupancy target: 3 wavefronts per SIMD with float buffers and float
@@ -281,7 +286,6 @@ __global__ __launch_bounds__(BLOCK) void adjoint_wall_kernel(AdjointArgs a) {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (t >= 6 * a.lx) return;
     L *__restrict__ lam = static_cast<L *>(a.lam_out);
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
     const int xg = t % a.lx, row = t / a.lx;      // row = side * 3 + i
     const int k = row < 3 ? -1 - row : a.lz + (row - 3);
     const GT *gh = static_cast<const GT *>(a.ghost) + (size_t)row * Q;
@@ -295,7 +299,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_wall_kernel(AdjointArgs a) {
         const int o = (m & 1) ? m + 1 : m - 1;
         const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
         S += c;
-        A += c * (double)lam[(size_t)o * N + (size_t)xd * (size_t)a.lz + (size_t)zd];
+        A += c * (double)lam[pidx(o, xd, zd, a.lx)];
     }
     const L out = (L)(A / S);
 #pragma unroll
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_wall_kernel(AdjointArgs a) {
         const int zs = k - EZ[m];   // population m streams into the ghost site from (xg - e_mx, zs)
         if (zs < 0 || zs >= a.lz) continue;
         const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
-        lam[(size_t)m * N + (size_t)xs * (size_t)a.lz + (size_t)zs] = out;
+        lam[pidx(m, xs, zs, a.lx)] = out;
     }
 }
 
@@ -363,14 +367,14 @@ static ObjLayout obj_layout(int lx, int lz) {
 size_t objective_scratch_bytes(int lx, int lz) { return obj_layout(lx, lz).total; }
 
 template <int PREC>
-__device__ __forceinline__ void site_moments(const void *fp, size_t N, size_t site, double &rho, double &ux,
+__device__ __forceinline__ void site_moments(const void *fp, int lx, int x, int z, double &rho, double &ux,
                                              double &uz, double &T) {
     using E = typename std::conditional<PREC == P_F64, double, float>::type;
-    const E *f = static_cast<const E *>(fp);
+    const E *f = static_cast<const E *>(fp) + pidx(0, x, z, lx);
     double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const double v = (double)f[(size_t)l * N + site];
+        const double v = (double)f[(size_t)l * TILE];
         s0 += v;
         if (EX[l] != 0) sx += EX[l] * v;
         if (EZ[l] != 0) sz += EZ[l] * v;
@@ -392,13 +396,12 @@ __global__ __launch_bounds__(BLOCK) void objective_pass1(ObjectiveArgs a, ObjLay
     double *kpart = reinterpret_cast<double *>(sc + L.kpart);
     const int zb = blockIdx.x % L.nzb, xc = blockIdx.x / L.nzb;
     const int tid = threadIdx.x, z = zb * BLOCK + tid;
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
     double tacc = 0.0, ke = 0.0;
     if (z < a.lz) {
         const int x1 = min(xc * OXC + OXC, a.lx);
         for (int x = xc * OXC; x < x1; ++x) {
             double rho, ux, uz, T;
-            site_moments<PREC>(a.f, N, (size_t)x * a.lz + z, rho, ux, uz, T);
+            site_moments<PREC>(a.f, a.lx, x, z, rho, ux, uz, T);
             const double uhz = uz + 0.5 * a.g;                 // u^H = u* - g_vec/2
             tacc += T + a.g * a.g / (4.0 * D);                  // T^H
             ke += 0.5 * rho * (ux * ux + uhz * uhz);
@@ -467,9 +470,9 @@ __global__ __launch_bounds__(BLOCK) void objective_seed(ObjectiveArgs a, ObjLayo
     const double *dtbar = reinterpret_cast<const double *>(static_cast<char *>(a.scratch) + L.dtbar);
     const int x = blockIdx.x / L.nzb, z = (blockIdx.x % L.nzb) * BLOCK + threadIdx.x;
     if (z >= a.lz) return;
-    const size_t N = (size_t)a.lx * (size_t)a.lz, site = (size_t)x * a.lz + z;
+    const size_t base = pidx(0, x, z, a.lx);
     double rho, ux, uz, T;
-    site_moments<PREC>(a.f, N, site, rho, ux, uz, T);
+    site_moments<PREC>(a.f, a.lx, x, z, rho, ux, uz, T);
     const double uhz = uz + 0.5 * a.g;
     const double g_rho = 0.5 * a.wk * (ux * ux + uhz * uhz);
     const double gux = a.wk * rho * ux, guz = a.wk * rho * uhz;
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(BLOCK) void objective_seed(ObjectiveArgs a, ObjLayo
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
         const double cx = R * EX[l] - ux, cz = R * EZ[l] - uz;
-        lam_seed[(size_t)l * N + site] =
+        lam_seed[base + (size_t)l * TILE] =
             (LT)(g_rho + (gux * cx + guz * cz) * inv + g_t * (cx * cx + cz * cz - D * T) * idr);
     }
 }
@@ -553,7 +556,6 @@ __global__ __launch_bounds__(BLOCK) void init_vjp_columns(InitVjpArgs a) {
     __shared__ double red[BLOCK];
     __shared__ double heights[2];
     const int x = blockIdx.x, tid = threadIdx.x;
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
     if (tid < 2) {
         double h = tid == 0 ? a.z_lo : a.z_hi;
         for (int j = 0; j < a.nmodes; ++j)
@@ -586,11 +588,11 @@ __global__ __launch_bounds__(BLOCK) void init_vjp_columns(InitVjpArgs a) {
 
             double g_lp = 0.0, g_tdir = 0.0;
             if (in && i >= 3) {
-                const size_t site = (size_t)x * a.lz + (size_t)(i - 3);
+                const size_t base = pidx(0, x, i - 3, a.lx);
                 const double rho = a.norm * exp(lp) / T;
                 double lam[Q];
 #pragma unroll
-                for (int l = 0; l < Q; ++l) lam[l] = (double)lam0[(size_t)l * N + site];
+                for (int l = 0; l < Q; ++l) lam[l] = (double)lam0[base + (size_t)l * TILE];
                 const double th = T - a.g * a.g / (4.0 * D) - 1.0;
                 const EqVjp s = eq_vjp_sums<double>(lam, 0.0, -0.5 * a.g, th);
                 const double g_rho = s.sp, g_teq = rho * s.sth;

@@ -55,9 +55,11 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     return a0 < b0 + nb && b0 < a0 + na;
 }
 
-size_t state_bytes(const lbm_params *p) {
-    return (size_t)LBM_Q * (size_t)p->lx * (size_t)p->lz * (size_t)elt_size(p->precision);
+// elements of a population buffer (state or adjoint) in the tiled layout
+size_t pop_elems(const lbm_params *p) {
+    return (size_t)LBM_Q * (size_t)p->lx * (size_t)lbm::tile_count(p->lz) * (size_t)lbm::TILE;
 }
+size_t state_bytes(const lbm_params *p) { return pop_elems(p) * (size_t)elt_size(p->precision); }
 size_t ghost_bytes(const lbm_params *p) { return (size_t)2 * 3 * LBM_Q * elt_size(p->precision); }
 size_t field_bytes(const lbm_params *p) { return (size_t)4 * p->lx * p->lz * sizeof(double); }
 // the step's moments output / the adjoint's moments input: double, or float with LBM_MOM_F32
@@ -149,7 +151,7 @@ int static_scratch(void **ptr) {
 }
 
 size_t lam_bytes(const lbm_params *p) {
-    return (size_t)LBM_Q * p->lx * p->lz * ((p->flags & LBM_ADJ_F32) ? sizeof(float) : sizeof(double));
+    return pop_elems(p) * ((p->flags & LBM_ADJ_F32) ? sizeof(float) : sizeof(double));
 }
 size_t vjp_scratch_bytes(int lx) { return ((size_t)2 * lx * sizeof(double) + 255) & ~size_t(255); }
 
@@ -183,6 +185,39 @@ int lbm_lattice(double *r, double *w, int32_t *e) {
         }
     }
     return LBM_OK;
+}
+
+size_t lbm_population_elems(const lbm_params *p) {
+    bool empty = false;
+    if (check_params(p, &empty) != LBM_OK) return 0;
+    return pop_elems(p);
+}
+
+static int layout_call(const lbm_params *p, const void *src, void *dst, int elt, bool pack, lbm_stream_t stream) {
+    bool empty = false;
+    int st = check_params(p, &empty);
+    if (st != LBM_OK) return st;
+    if (!src || !dst || (elt != 4 && elt != 8)) return LBM_EINVAL;
+    if (!aligned(src, (size_t)elt) || !aligned(dst, (size_t)elt)) return LBM_EALIGN;
+    if (empty) return LBM_OK;
+    const size_t soa = (size_t)LBM_Q * (size_t)p->lx * (size_t)p->lz * (size_t)elt;
+    const size_t tiled = pop_elems(p) * (size_t)elt;
+    if (overlap(src, pack ? soa : tiled, dst, pack ? tiled : soa)) return LBM_EALIAS;
+    lbm::LayoutArgs a;
+    a.src = src;
+    a.dst = dst;
+    a.lx = p->lx;
+    a.lz = p->lz;
+    a.elt = elt;
+    return hip_status(lbm::launch_layout(a, pack, (hipStream_t)stream));
+}
+
+int lbm_pack(const lbm_params *p, const void *soa, void *tiled, int elt_bytes, lbm_stream_t stream) {
+    return layout_call(p, soa, tiled, elt_bytes, true, stream);
+}
+
+int lbm_unpack(const lbm_params *p, const void *tiled, void *soa, int elt_bytes, lbm_stream_t stream) {
+    return layout_call(p, tiled, soa, elt_bytes, false, stream);
 }
 
 size_t lbm_scratch_bytes(const lbm_params *p) {

@@ -90,6 +90,38 @@ __device__ __forceinline__ void stg_off_nt(T *base, uint32_t byte_off, T v) {
     __builtin_nontemporal_store(v, reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off));
 }
 
+// Tiled layout of population buffers (the state and the adjoint buffers).
+// Rows are grouped in tiles of TILE; tile zt of column x holds its 37
+// populations as 37 consecutive runs of TILE elements:
+//     element (l, x, z) at ((zt Lx + x) 37 + l) TILE + (z - zt TILE),  zt = z / TILE,
+// for z in [0, Lz); the rows of the last tile from Lz up are padding.  A
+// wavefront's 37 + 37 memory streams then lie within a few contiguous
+// 37 TILE-element tiles instead of 37 + 37 arrays a whole lattice apart,
+// which keeps the per-CU address-translation cache from thrashing.
+constexpr int TILE = 512;
+static_assert((TILE & (TILE - 1)) == 0, "TILE is a power of two");
+
+__host__ __device__ __forceinline__ int tile_count(int lz) { return (lz + TILE - 1) / TILE; }
+
+// Index of element (l, x, z), 0 <= z < Lz.
+__host__ __device__ __forceinline__ size_t pidx(int l, int x, int z, int lx) {
+    const unsigned uz = (unsigned)z;
+    return (((size_t)(uz / TILE) * (size_t)lx + (size_t)x) * Q + (size_t)l) * TILE + (size_t)(uz % TILE);
+}
+
+// Index of element (l, x, z0 + r) for a block whose rows [z0, z0 + n) lie in
+// one tile (z0 / TILE block-uniform) and -TILE <= r - (z0 % TILE) < 2 TILE:
+// the row may sit in the tile below or above (pulls and pushes shifted by
+// up to 3 rows).  `base` is the index of (0, x, zt TILE), `step` the index
+// distance between tiles zt and zt + 1 of one column less TILE.
+__device__ __forceinline__ long long tile_off(int l, int rl, long long step) {
+    // rl = row within tile zt, possibly -3 .. TILE + 2
+    long long off = (long long)l * TILE + rl;
+    if (rl < 0) off -= step;
+    if (rl >= TILE) off += step;
+    return off;
+}
+
 // Wrap an index into [0, n) for any integer (periodic directions).
 __device__ __forceinline__ int wrap(int i, int n) {
     int m = i % n;

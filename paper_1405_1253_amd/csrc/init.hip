@@ -19,16 +19,18 @@ __device__ __forceinline__ double layer_t(const InitArgs &a, double zc, double h
     return a.t_d + (a.t_m - a.t_d) * s0 + (a.t_u - a.t_m) * s1;
 }
 
+// The 37 populations of one site: element l at index base + l * stride
+// (tiled state: stride TILE; wall table: stride 1).
 template <int PREC>
-__device__ __forceinline__ void store_state(void *f, size_t N, size_t site, const double feq[Q]) {
+__device__ __forceinline__ void store_state(void *f, size_t base, size_t stride, const double feq[Q]) {
     if (PREC == P_F64) {
         double *o = static_cast<double *>(f);
 #pragma unroll
-        for (int l = 0; l < Q; ++l) o[(size_t)l * N + site] = feq[l];
+        for (int l = 0; l < Q; ++l) o[base + (size_t)l * stride] = feq[l];
     } else {
         float *o = static_cast<float *>(f);
 #pragma unroll
-        for (int l = 0; l < Q; ++l) o[(size_t)l * N + site] = (float)(feq[l] - W[l]);
+        for (int l = 0; l < Q; ++l) o[base + (size_t)l * stride] = (float)(feq[l] - W[l]);
     }
 }
 
@@ -38,7 +40,6 @@ __global__ __launch_bounds__(BLOCK) void init_columns(InitArgs a) {
     __shared__ double heights[2];
     const int x = blockIdx.x;
     const int tid = threadIdx.x;
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
 
     if (tid < 2) {
         double h = tid == 0 ? a.z_lo : a.z_hi;
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(BLOCK) void init_columns(InitArgs a) {
             const double rho = a.norm * exp(lnp) / T;
             double feq[Q];
             equilibrium_f64(rho, 0.0, -0.5 * a.g, T - a.g * a.g / (4.0 * D), feq);
-            store_state<PREC>(a.f_out, N, (size_t)x * (size_t)a.lz + (size_t)(i - 3), feq);
+            store_state<PREC>(a.f_out, pidx(0, x, i - 3, a.lx), TILE, feq);
         }
     }
 }
@@ -91,7 +92,7 @@ __global__ void init_ghost(InitArgs a) {
     if (i >= 6) return;
     double feq[Q];
     equilibrium_f64(a.ghost_rho[i], 0.0, -0.5 * a.g, a.ghost_t[i] - a.g * a.g / (4.0 * D), feq);
-    store_state<PREC>(a.ghost_out, 1, (size_t)i * Q, feq);   // element (i, l) at i*37 + l
+    store_state<PREC>(a.ghost_out, (size_t)i * Q, 1, feq);   // element (i, l) at i*37 + l
 }
 
 hipError_t launch_init(const InitArgs &a, int precision, hipStream_t s) {

@@ -100,4 +100,13 @@ struct InitVjpArgs {
 };
 hipError_t launch_init_vjp(const InitVjpArgs &a, hipStream_t s);
 
+struct LayoutArgs {
+    const void *src;
+    void *dst;
+    int lx, lz;
+    int elt;               // element size in bytes, 4 or 8
+};
+// pack: [37][Lx][Lz] -> tiled (padding rows zeroed); unpack: tiled -> [37][Lx][Lz]
+hipError_t launch_layout(const LayoutArgs &a, bool pack, hipStream_t s);
+
 }  // namespace lbm

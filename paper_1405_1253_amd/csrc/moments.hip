@@ -39,11 +39,12 @@ __global__ __launch_bounds__(BLOCK) void moments_pass1(MomentArgs a, int nzb, do
     double tacc = 0.0, m0 = 0.0, mx = 0.0, mz = 0.0, me = 0.0;
     if (active) {
         for (int x = x0; x < x1; ++x) {
-            const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;
+            const size_t site = (size_t)x * (size_t)a.lz + (size_t)z;   // fields: [4][Lx][Lz]
+            const size_t base = pidx(0, x, z, a.lx);                     // state: tiled
             double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
 #pragma unroll
             for (int l = 0; l < Q; ++l) {
-                const double v = (double)f[(size_t)l * N + site];
+                const double v = (double)f[base + (size_t)l * TILE];
                 s0 += v;
                 if (EX[l] != 0) sx += EX[l] * v;
                 if (EZ[l] != 0) sz += EZ[l] * v;
@@ -135,14 +136,14 @@ hipError_t launch_moments(const MomentArgs &a, int precision, hipStream_t s) {
 // row profiles: mean and rms fluctuation of T^H and E_k = rho |u^H|^2 / 2
 // ---------------------------------------------------------------------------
 template <int PREC>
-__device__ __forceinline__ void site_th_ek(const void *fp, size_t N, size_t site, double g, double &th,
+__device__ __forceinline__ void site_th_ek(const void *fp, int lx, int x, int z, double g, double &th,
                                            double &ek) {
     using E = typename std::conditional<PREC == P_F64, double, float>::type;
-    const E *f = static_cast<const E *>(fp);
+    const E *f = static_cast<const E *>(fp) + pidx(0, x, z, lx);
     double s0 = 0.0, sx = 0.0, sz = 0.0, s2 = 0.0;
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-        const double v = (double)f[(size_t)l * N + site];
+        const double v = (double)f[(size_t)l * TILE];
         s0 += v;
         if (EX[l] != 0) sx += EX[l] * v;
         if (EZ[l] != 0) sz += EZ[l] * v;
@@ -169,14 +170,13 @@ __global__ __launch_bounds__(BLOCK) void profiles_pass1(ProfileArgs a, int nzb, 
     const int zb = blockIdx.x % nzb, xc = blockIdx.x / nzb;
     const int z = zb * BLOCK + threadIdx.x;
     if (z >= a.lz) return;
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
     double t0, e0;
-    site_th_ek<PREC>(a.f, N, (size_t)z, a.g, t0, e0);
+    site_th_ek<PREC>(a.f, a.lx, 0, z, a.g, t0, e0);
     double st = 0.0, stt = 0.0, se = 0.0, see = 0.0;
     const int x1 = min(xc * XC + XC, a.lx);
     for (int x = xc * XC; x < x1; ++x) {
         double th, ek;
-        site_th_ek<PREC>(a.f, N, (size_t)x * a.lz + z, a.g, th, ek);
+        site_th_ek<PREC>(a.f, a.lx, x, z, a.g, th, ek);
         const double dt = th - t0, de = ek - e0;
         st += dt;
         stt += dt * dt;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(BLOCK) void profiles_pass2(ProfileArgs a, int nxc) 
     for (int c = 0; c < nxc; ++c)
         for (int k = 0; k < 4; ++k) m[k] += part[k * stride + (size_t)c * a.lz + z];
     double t0, e0;
-    site_th_ek<PREC>(a.f, (size_t)a.lx * (size_t)a.lz, (size_t)z, a.g, t0, e0);
+    site_th_ek<PREC>(a.f, a.lx, 0, z, a.g, t0, e0);
     const double inv = 1.0 / (double)a.lx;
     const double mt = m[0] * inv, me = m[2] * inv;
     a.prof[z] = t0 + mt;

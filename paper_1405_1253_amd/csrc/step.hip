@@ -3,16 +3,20 @@
 // Sec. III.A eq. LBE and the shifted equilibrium; Sec. III.B step order
 // (propagate, bc, collide) and the prv/nxt pair of lattice copies.
 //
-// Mapping.  One thread per site; a block covers BS consecutive sites of one
-// column (z fastest) and walks ZT such tiles down the column, so every
-// population access of a wavefront is a contiguous 512-byte (FP64) or
-// 256-byte (FP32) run.  The pull source of
-// population l is column (x - e_lx) mod Lx, rows z - e_lz: the column offset
-// is uniform over the block (scalar), the row shift is an immediate offset.
-// Each input element is read by exactly one site, so the step moves
-// 37 reads + 37 writes per site and is bound by HBM bandwidth; the arithmetic
-// (~500 flops per site with the factored equilibrium) stays well under the
-// FP64 ridge.
+// Mapping.  Populations are stored in the tiled layout of common.h (tiles of
+// TILE rows, a tile's 37 populations contiguous).  One thread per site; a
+// block covers one tile of one column, so every population access of a
+// wavefront is a contiguous 512-byte (FP64) or 256-byte (FP32) run, and
+// consecutive blocks take consecutive tiles of a column.  The pull source of
+// population l is column (x - e_lx) mod Lx, row z - e_lz: in an interior
+// tile that is the same tile of the source column or, for the |e_lz| rows at
+// the tile's edge, the tile below or above it.  Each input element is read
+// by exactly one site, so the step moves 37 reads + 37 writes per site and is
+// bound by HBM bandwidth; the arithmetic (~500 flops per site with the
+// factored equilibrium) stays well under the FP64 ridge.  In the
+// [37][Lx][Lz] layout a wavefront's 74 streams touched 74 pages a whole
+// population array apart and thrashed the CU's address-translation cache;
+// in tiles they lie within a few neighbouring 37 TILE-element runs.
 //
 // Walls.  Blocks within 3 rows of either wall (or of a ragged end) take a
 // second, block-uniform code path that substitutes ghost sites for sources
@@ -97,7 +101,6 @@ __device__ __forceinline__ double full_value(E v, int l) {
 template <int PREC, typename E>
 __device__ __forceinline__ double ghost_ratio(const StepArgs &a, const E *f, const E *ghost, int side, int i,
                                               int xg) {
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
     const int k = side == 0 ? -1 - i : a.lz + i;
     const E *row = ghost + (size_t)(side * 3 + i) * Q;
     double M = 0.0, S = 0.0;
@@ -106,7 +109,7 @@ __device__ __forceinline__ double ghost_ratio(const StepArgs &a, const E *f, con
         const int zs = k - EZ[m];
         if (zs >= 0 && zs < a.lz) {
             const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
-            M += full_value<PREC>(f[(size_t)m * N + (size_t)xs * (size_t)a.lz + (size_t)zs], m);
+            M += full_value<PREC>(f[pidx(m, xs, zs, a.lx)], m);
         }
         const int zd = k + EZ[m];
         if (zd >= 0 && zd < a.lz) S += full_value<PREC>(row[m], m);
@@ -134,7 +137,7 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                                           const double (*ratio)[3][7]) {
     using E = typename Elt<PREC>::T;
     constexpr bool two = MODE == M_PULL;
-    const size_t N = (size_t)a.lx * (size_t)a.lz;
+    const size_t N = (size_t)a.lx * (size_t)a.lz;   // moments_out is [4][Lx][Lz]
     typename Ptr<const E, two>::type fin = static_cast<const E *>(two ? a.f_in : a.f_out);
     typename Ptr<E, two>::type fout = static_cast<E *>(a.f_out);
     const E *__restrict__ ghost = static_cast<const E *>(a.ghost);
@@ -144,12 +147,18 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
     const bool periodic = (a.flags & F_PERIODIC_Z) != 0;
 
     // ---- propagate + bc: the incoming population l ------------------------
+    // Interior tiles of the two-buffer step address rows relative to this
+    // block's tile (one tile per block: zt is uniform); every other path
+    // uses the general tiled index.
+    const int zt = two && !EDGE ? __builtin_amdgcn_readfirstlane(z / TILE) : 0;
+    const int zl = z % TILE;
+    const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
     auto gather = [&](int l) -> E {
         // in-range value: pulled from the neighbour, or (IN_E) this site's -l slot
         const int xs = (MODE == M_IN_E || EX[l] == 0) ? x : wrap(x - EX[l], a.lx);
-        const E *src = fin + (size_t)(MODE == M_IN_E ? opp(l) : l) * N + (size_t)xs * (size_t)a.lz;
+        const int sl = MODE == M_IN_E ? opp(l) : l;
         const int dz = MODE == M_IN_E ? 0 : EZ[l];
-        if (!EDGE) return src[z - dz];
+        if (!EDGE) return fin[pidx(sl, xs, z - dz, a.lx)];
         const int zs = zq - EZ[l];   // pull source row: beyond a wall -> ghost site
         if (diffuse) {
             if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
@@ -157,12 +166,12 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) * ratio[side][i][3 - EX[l]];
                 return (E)(PREC == P_F64 ? f : f - W[l]);
             }
-            return src[zq - dz];
+            return fin[pidx(sl, xs, zq - dz, a.lx)];
         }
-        if (periodic) return src[wrap(zq - dz, a.lz)];
+        if (periodic) return fin[pidx(sl, xs, wrap(zq - dz, a.lz), a.lx)];
         if (zs < 0) return ghost[(-zs - 1) * Q + l];
         if (zs >= a.lz) return ghost[(3 + zs - a.lz) * Q + l];
-        return src[zq - dz];
+        return fin[pidx(sl, xs, zq - dz, a.lx)];
     };
     // All 37 populations are held in registers from the gather to the stores;
     // in place, a pair's stores overwrite only that pair's own inputs (the
@@ -176,10 +185,12 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
 #pragma unroll
         for (int l = 0; l < Q; ++l) {
             const int xs = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
-            const E *src = fin + (size_t)l * N + (size_t)xs * (size_t)a.lz;
             if (!EDGE) {
-                v[l] = src[z - EZ[l]];
+                // row z - e_lz: this tile, or (|e_lz| rows) the one below / above
+                const E *tb = fin + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
+                v[l] = tb[tile_off(l, zl - EZ[l], tstep)];
             } else {
+                auto src = [&](int zz) -> E { return fin[pidx(l, xs, zz, a.lx)]; };
                 const int zs = zq - EZ[l];
                 if (diffuse) {
                     if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
@@ -188,16 +199,16 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                                          ratio[side][i][3 - EX[l]];
                         v[l] = (E)(PREC == P_F64 ? f : f - W[l]);
                     } else {
-                        v[l] = src[zs];
+                        v[l] = src(zs);
                     }
                 } else if (periodic) {
-                    v[l] = src[wrap(zs, a.lz)];
+                    v[l] = src(wrap(zs, a.lz));
                 } else if (zs < 0) {
                     v[l] = ghost[(-zs - 1) * Q + l];
                 } else if (zs >= a.lz) {
                     v[l] = ghost[(3 + zs - a.lz) * Q + l];
                 } else {
-                    v[l] = src[zs];
+                    v[l] = src(zs);
                 }
             }
         }
@@ -213,25 +224,28 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
     // written back (measured 3 % faster on MI355X).
     auto put = [&](int l, E val) {
         if (MODE == M_PULL) {
-            __builtin_nontemporal_store(val, &fout[(size_t)l * N + site]);
+            if (!EDGE)
+                __builtin_nontemporal_store(
+                    val, &fout[((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)l * TILE + zl]);
+            else
+                __builtin_nontemporal_store(val, &fout[pidx(l, x, z, a.lx)]);
             return;
         }
         if (MODE == M_IN_E) {
-            fout[(size_t)l * N + site] = val;
+            fout[pidx(l, x, z, a.lx)] = val;
             return;
         }
         const int xd = EX[l] == 0 ? x : wrap(x + EX[l], a.lx);
-        E *dst = fout + (size_t)opp(l) * N + (size_t)xd * (size_t)a.lz;
+        const int zd = z + EZ[l];
         if (!EDGE) {
-            dst[z + EZ[l]] = val;
+            fout[pidx(opp(l), xd, zd, a.lx)] = val;
         } else {
-            const int zd = z + EZ[l];
             if (periodic)
-                dst[wrap(zd, a.lz)] = val;
+                fout[pidx(opp(l), xd, wrap(zd, a.lz), a.lx)] = val;
             else if (zd < 0 || zd >= a.lz)
-                fout[(size_t)l * N + site] = val;
+                fout[pidx(l, x, z, a.lx)] = val;
             else
-                dst[zd] = val;
+                fout[pidx(opp(l), xd, zd, a.lx)] = val;
         }
     };
 
@@ -360,12 +374,15 @@ template <int PREC>
 struct StepShape;
 template <>
 struct StepShape<P_F64> {
-    static constexpr int BS = 512, ZT = 2;
+    static constexpr int BS = TILE, ZT = 1;
 };
 template <>
 struct StepShape<P_F32_DEV> {
-    static constexpr int BS = 256, ZT = 2;
+    static constexpr int BS = TILE, ZT = 1;
 };
+static_assert(StepShape<P_F64>::BS * StepShape<P_F64>::ZT == TILE &&
+                  StepShape<P_F32_DEV>::BS * StepShape<P_F32_DEV>::ZT == TILE,
+              "a block of the two-buffer step covers exactly one tile (the interior path's addressing)");
 
 // Diffuse-wall rows of one column per wavefront (two-buffer step).  Lanes
 // 0..41 evaluate M/S of the 2 x 3 x 7 ghost sites the column pulls from, then
@@ -400,7 +417,7 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, i
         wall_block<PREC, BS>(a, blockIdx.x);
         return;
     }
-    const uint32_t t = xcd_tile(blockIdx.x - nwall, nblocks);
+    const uint32_t t = blockIdx.x - nwall;
     const int x = (int)(t / (uint32_t)nzb);
     const int zt = (int)(t % (uint32_t)nzb) * ZT;
     const bool skip_wall = nwall != 0;

@@ -109,8 +109,7 @@ class Rollout:
         self.ldtype = torch.float32 if c.adj_precision == "f32" else torch.float64
         self.desc = abi.RT3Desc(c.t_d, c.t_m, c.t_u, c.width, c.k, c.phase)
         self.sdtype = torch.float64 if c.precision == "f64" else torch.float32
-        shape = (abi.Q, c.lx, c.lz)
-        self.buf = [torch.empty(shape, dtype=self.sdtype, device=self.device) for _ in range(2)]
+        self.buf = [abi.empty_populations(self.params, self.sdtype, self.device) for _ in range(2)]
         self.ghost = torch.empty((2, 3, abi.Q), dtype=self.sdtype, device=self.device)
         self.scratch = torch.empty(max(abi.lbm_scratch_bytes(self.params), 256), dtype=torch.uint8,
                                    device=self.device)
@@ -156,8 +155,7 @@ class Rollout:
                 self._save(t, self.buf[cur])
         self.final = self.buf[cur]
         self.j = torch.empty(5, dtype=torch.float64, device=self.device)
-        self.lam = [torch.empty((abi.Q, c.lx, c.lz), dtype=self.ldtype, device=self.device)
-                    for _ in range(2)]
+        self.lam = [abi.empty_populations(self.params, self.ldtype, self.device) for _ in range(2)]
         abi.lbm_objective(self.params, self.desc, self.final, c.wk, c.wl, self.j, self.lam[0],
                           self.scratch)
         return self.j

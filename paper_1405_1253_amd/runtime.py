@@ -1,5 +1,8 @@
 """Lattice: device buffers and stream plumbing around the C entry points.
 
+Population buffers are in the library's tiled layout; ``state_soa()``,
+``populations()`` and ``set_state()`` convert from and to [37, Lx, Lz].
+
 Owns the prv/nxt pair of population buffers (Sec. III.B) -- or, with
 ``inplace=True``, a single buffer stepped by lbm_step_inplace -- the wall
 table and the diagnostics scratch, all as torch tensors on one GPU; every
@@ -23,7 +26,7 @@ class Lattice:
                                       abi.F64 if precision == "f64" else abi.F32_DEV, flags)
         self.device = torch.device(device)
         self.inplace = inplace
-        self.buf = [torch.empty((abi.Q, lx, lz), dtype=self.dtype, device=self.device)
+        self.buf = [abi.empty_populations(self.params, self.dtype, self.device)
                     for _ in range(1 if inplace else 2)]
         self.cur = 0
         self.kind = abi.INPLACE_FROM_STATE   # in place: what the buffer holds
@@ -60,13 +63,25 @@ class Lattice:
     # ---- time stepping ----------------------------------------------------
     @property
     def state(self):
+        """The post-collision state buffer (library's tiled layout)."""
         if self.kind != abi.INPLACE_FROM_STATE:
             raise RuntimeError("the single buffer holds the streamed form after an odd number of "
                                "in-place steps; step once more to get the post-collision state")
         return self.buf[self.cur]
 
+    def state_soa(self):
+        """The stored state in the plain layout [37, lx, lz], element type of
+        the state (FP32 deviation storage: f - w); a bit-exact copy."""
+        return abi.to_soa(self.params, self.state)
+
     def set_state(self, f):
-        self.buf[self.cur].copy_(f)
+        """Set the post-collision state from a plain-layout [37, lx, lz] array
+        of the state's element type, or copy a tiled buffer of this lattice."""
+        if tuple(f.shape) == (abi.Q, self.lx, self.lz):
+            abi.lbm_pack(self.params, torch.as_tensor(f).to(self.device, self.dtype).contiguous(),
+                         self.buf[self.cur])
+        else:
+            self.buf[self.cur].copy_(f)
         self.kind = abi.INPLACE_FROM_STATE
 
     def step(self, n=1, moments_out=None):
@@ -120,7 +135,7 @@ class Lattice:
         parameters and step count (host tensors)."""
         return {"lx": self.lx, "lz": self.lz, "tau": self.tau, "g": self.g,
                 "precision": self.precision, "flags": int(self.params.flags),
-                "steps_done": self.steps_done, "state": self.state.cpu(),
+                "steps_done": self.steps_done, "state": self.state_soa().cpu(),
                 "ghost": self.ghost.cpu()}
 
     def save(self, path):
@@ -130,10 +145,9 @@ class Lattice:
     def from_state_dict(cls, d, device="cuda"):
         lat = cls(d["lx"], d["lz"], d["tau"], d["g"], precision=d["precision"],
                   flags=d["flags"], device=device)
-        lat.buf[0].copy_(d["state"])
-        lat.ghost.copy_(d["ghost"])
         lat.cur = 0
-        lat.kind = abi.INPLACE_FROM_STATE
+        lat.set_state(d["state"])
+        lat.ghost.copy_(d["ghost"])
         lat.steps_done = d["steps_done"]
         return lat
 
@@ -142,8 +156,9 @@ class Lattice:
         return cls.from_state_dict(torch.load(path, weights_only=True), device=device)
 
     def populations(self):
-        """Full populations f_l as float64 (adds the weights back in FP32 mode)."""
-        f = self.state.to(torch.float64)
+        """Full populations f_l as float64, plain layout [37, lx, lz] (adds the
+        weights back in FP32 mode)."""
+        f = self.state_soa().to(torch.float64)
         if self.precision == "f32dev":
             _, w, _ = abi.lbm_lattice()
             f = f + torch.as_tensor(w, device=self.device)[:, None, None]

@@ -200,7 +200,7 @@ def test_binding_constants_match_the_header():
     from paper_1405_1253_amd import abi as mod
     h = header_constants()
     assert h["LBM_ABI_VERSION"] == mod.ABI_VERSION and h["LBM_Q"] == mod.Q
-    assert h["LBM_MAX_MODES"] == mod.MAX_MODES
+    assert h["LBM_MAX_MODES"] == mod.MAX_MODES and h["LBM_TILE"] == mod.TILE
     for name in ("F64", "F32_DEV", "PERIODIC_Z", "NO_COLLIDE", "ADJ_F32", "WALL_DIFFUSE", "MOM_F32",
                  "INPLACE_FROM_STATE", "INPLACE_FROM_STREAMED"):
         assert h["LBM_" + name] == getattr(mod, name), name
@@ -220,8 +220,10 @@ def test_binding_rejects_mismatched_buffers():
     lx, lz = 4, 9
     p64 = A.make_params(lx, lz, 0.7, 1e-4)
     p32 = A.make_params(lx, lz, 0.7, 1e-4, A.F32_DEV)
-    st64 = torch.zeros((37, lx, lz), dtype=torch.float64)
-    st32 = torch.zeros((37, lx, lz), dtype=torch.float32)
+    n = A.population_elems(p64)
+    assert n == 37 * lx * 512                 # one tile of 512 rows per column
+    st64 = torch.zeros(n, dtype=torch.float64)
+    st32 = torch.zeros(n, dtype=torch.float32)
     gh64 = torch.zeros((2, 3, 37), dtype=torch.float64)
     gh32 = torch.zeros((2, 3, 37), dtype=torch.float32)
     mom64 = torch.zeros((4, lx, lz), dtype=torch.float64)
@@ -232,7 +234,10 @@ def test_binding_rejects_mismatched_buffers():
         lambda: A.lbm_step(p64, gh32, st64, st64.clone()),             # float wall table
         lambda: A.lbm_step(p64, gh64, st64, st64.clone(), mom32),      # float moments, no MOM_F32
         lambda: A.lbm_step(A.make_params(lx, lz, 0.7, 1e-4, flags=A.MOM_F32), gh64, st64, st64.clone(), mom64),
-        lambda: A.lbm_step(p64, gh64, st64[:, :, :8].contiguous(), st64.clone()),   # too short
+        lambda: A.lbm_step(p64, gh64, st64[:-1].contiguous(), st64.clone()),      # too short
+        lambda: A.lbm_step(p64, gh64, torch.zeros((37, lx, lz), dtype=torch.float64), st64.clone()),  # plain layout
+        lambda: A.lbm_pack(p64, torch.zeros((37, lx, lz), dtype=torch.float64), st32),  # element sizes differ
+        lambda: A.lbm_unpack(p64, st64[:100].contiguous(), torch.zeros((37, lx, lz), dtype=torch.float64)),
         lambda: A.lbm_step_inplace(p64, gh64, st32, A.INPLACE_FROM_STATE),
         lambda: A.lbm_moments(p64, st64, fields=mom32),
         lambda: A.lbm_moments(p64, st64, tbar=torch.zeros(lz - 1, dtype=torch.float64)),
@@ -257,3 +262,25 @@ def test_binding_rejects_mismatched_buffers():
     # matching buffers pass the check and reach the GPU-tensor check instead
     with pytest.raises(ValueError, match="GPU tensors"):
         A.lbm_step(p64, gh64, st64, st64.clone(), mom64)
+
+
+def test_population_buffer_size_and_layout_index():
+    """lbm_population_elems against the binding's formula, and the tiled
+    index of include/lbm.h (element (l, x, z) at ((zt Lx + x) 37 + l) 512 +
+    z - 512 zt) as a bijection of the [37][Lx][Lz] elements onto the buffer
+    minus its padding rows."""
+    from paper_1405_1253_amd import abi as A
+    lib = A.load()
+    for lx, lz in ((1, 1), (3, 7), (4, 512), (5, 513), (2, 1100), (4096, 12288), (16384, 32768)):
+        p = A.make_params(lx, lz, 0.7, 0.0)
+        assert lib.lbm_population_elems(ctypes.byref(p)) == A.population_elems(p) == 37 * lx * (-(-lz // 512)) * 512
+    lx, lz = 3, 1100
+    l, x, z = np.meshgrid(np.arange(37), np.arange(lx), np.arange(lz), indexing="ij")
+    idx = (((z // 512) * lx + x) * 37 + l) * 512 + z % 512
+    assert len(np.unique(idx)) == idx.size
+    assert idx.max() < A.population_elems(A.make_params(lx, lz, 0.7, 0.0))
+    # the tiled_view / column helpers read the same index
+    import torch
+    t = torch.arange(A.population_elems(A.make_params(lx, lz, 0.7, 0.0)), dtype=torch.float64)
+    p = A.make_params(lx, lz, 0.7, 0.0)
+    assert np.array_equal(A.column(p, t, 2).numpy(), idx[:, 2, :].astype(np.float64))

@@ -29,6 +29,16 @@ def _t(a):
     return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
 
 
+def _pop(abi, a):
+    """Plain-layout [37, lx, lz] array -> tiled device buffer."""
+    return abi.to_tiled(abi.make_params(a.shape[1], a.shape[2], 0.7, 0.0), a)
+
+
+def _np(abi, lx, lz, t):
+    """Tiled device buffer -> plain-layout [37, lx, lz] numpy array."""
+    return abi.to_soa(abi.make_params(lx, lz, 0.7, 0.0), t).cpu().numpy()
+
+
 def _rel_max(got, want):
     return float(np.abs(got - want).max() / np.abs(want).max())
 
@@ -52,13 +62,13 @@ def test_adjoint_step_parity(abi, lx, lz, mode):
     flags = ((abi.PERIODIC_Z if p.periodic_z else 0) | (abi.NO_COLLIDE if p.no_collide else 0)
              | abi.wall_flag(p.wall))
     params = abi.make_params(lx, lz, p.tau, p.g, flags=flags)
-    fin, gh = _t(f), _t(ghost)
+    fin, gh = _pop(abi, f), _t(ghost)
     fout = torch.empty_like(fin)
     mom = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
     abi.lbm_step(params, gh, fin, fout, mom)
     lam_out = torch.full_like(fin, float("nan"))
-    abi.lbm_adjoint_step(params, gh, mom, _t(lam), lam_out)
-    got = lam_out.cpu().numpy()
+    abi.lbm_adjoint_step(params, gh, mom, _pop(abi, lam), lam_out)
+    got = _np(abi, lx, lz, lam_out)
     assert np.isfinite(got).all()
     assert _rel_max(got, want) <= 1e-12
 
@@ -69,9 +79,9 @@ def test_objective_and_seed_parity(abi):
     desc = abi.RT3Desc(1.05, 1.0, 0.95, 3.0)
     params = abi.make_params(lx, lz, p.tau, p.g)
     j = torch.empty(5, dtype=torch.float64, device=DEV)
-    seed = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
+    seed = abi.empty_populations(params, torch.float64)
     scratch = torch.empty(abi.lbm_scratch_bytes(params), dtype=torch.uint8, device=DEV)
-    abi.lbm_objective(params, desc, _t(f), 2.0, 0.5, j, seed, scratch)
+    abi.lbm_objective(params, desc, _pop(abi, f), 2.0, 0.5, j, seed, scratch)
     Jo, ke, L = O.objective(f, p, 0.95, 1.0, 1.05, 2.0, 0.5)
     got = j.cpu().numpy()
     assert L > 1.0 and ke > 0.0
@@ -80,7 +90,7 @@ def test_objective_and_seed_parity(abi):
     assert Lu > 0.5 and Ld > 0.5
     assert abs(got[3] / Lu - 1) <= 1e-12 and abs(got[4] / Ld - 1) <= 1e-12
     want = A.objective_vjp(f, p, 0.95, 1.0, 1.05, 2.0, 0.5)
-    assert _rel_max(seed.cpu().numpy(), want) <= 1e-12
+    assert _rel_max(_np(abi, lx, lz, seed), want) <= 1e-12
 
 
 def test_init_vjp_parity(abi):
@@ -94,7 +104,7 @@ def test_init_vjp_parity(abi):
         d_amp = torch.empty((2, nm), dtype=torch.float64, device=DEV)
         scratch = torch.empty(abi.lbm_scratch_bytes(params), dtype=torch.uint8, device=DEV)
         abi.lbm_init_rt3_vjp(params, abi.RT3Desc(1.05, 1.0, 0.95, 4.0, m.k, m.phase), _t(m.amp),
-                             _t(lam), d_amp, scratch)
+                             _pop(abi, lam), d_amp, scratch)
         assert _rel_max(d_amp.cpu().numpy(), want) <= 1e-12, (lx, lz)
 
 
@@ -179,13 +189,13 @@ def test_adjoint_step_float_buffers(abi, wall):
     lam = np.random.default_rng(8).standard_normal((37, lx, lz)).astype(np.float32)
     want = A.step_vjp(lam.astype(np.float64), f, ghost, p)
     params = abi.make_params(lx, lz, p.tau, p.g, flags=abi.ADJ_F32 | abi.wall_flag(wall))
-    fout = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
+    fout = abi.empty_populations(params, torch.float64)
     mom = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
     gh = _t(ghost)
-    abi.lbm_step(params, gh, _t(f), fout, mom)
-    out = torch.empty((37, lx, lz), dtype=torch.float32, device=DEV)
-    abi.lbm_adjoint_step(params, gh, mom, _t(lam), out)
-    assert _rel_max(out.cpu().numpy().astype(np.float64), want) <= (2.0 ** -23 if wall == "dirichlet"
+    abi.lbm_step(params, gh, _pop(abi, f), fout, mom)
+    out = abi.empty_populations(params, torch.float32)
+    abi.lbm_adjoint_step(params, gh, mom, _pop(abi, lam), out)
+    assert _rel_max(_np(abi, lx, lz, out).astype(np.float64), want) <= (2.0 ** -23 if wall == "dirichlet"
                                                                    else 3 * 2.0 ** -24)
 
 
@@ -218,7 +228,7 @@ def test_float_moments(abi):
     lx, lz = 128, 384
     p, f, ghost = _state(lx, lz, 0.7, 2e-3, 21)
     lam = np.random.default_rng(22).standard_normal((37, lx, lz))
-    fin, gh = _t(f), _t(ghost)
+    fin, gh = _pop(abi, f), _t(ghost)
     fout = torch.empty_like(fin)
     m64 = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
     m32 = torch.empty((4, lx, lz), dtype=torch.float32, device=DEV)
@@ -229,9 +239,9 @@ def test_float_moments(abi):
     assert torch.equal(m32, m64.float())
     out64 = torch.empty_like(fin)
     out32 = torch.empty_like(fin)
-    abi.lbm_adjoint_step(p64, gh, m64, _t(lam), out64)
-    abi.lbm_adjoint_step(p32, gh, m32, _t(lam), out32)
-    err = _rel_max(out32.cpu().numpy(), out64.cpu().numpy())
+    abi.lbm_adjoint_step(p64, gh, m64, _pop(abi, lam), out64)
+    abi.lbm_adjoint_step(p32, gh, m32, _pop(abi, lam), out32)
+    err = _rel_max(_np(abi, lx, lz, out32), _np(abi, lx, lz, out64))
     print(f"adjoint step with float moments: {err:.2e} of max")
     assert err <= 1e-6
 
@@ -252,17 +262,18 @@ def test_adjoint_step_all_float(abi, wall):
     lam = np.random.default_rng(24).standard_normal((37, lx, lz)).astype(np.float32)
     want = A.step_vjp(lam.astype(np.float64), f, ghost, p)
     flags = abi.MOM_F32 | abi.wall_flag(wall)
-    fin, gh = _t(f), _t(ghost)
+    fin, gh = _pop(abi, f), _t(ghost)
     fout = torch.empty_like(fin)
     m32 = torch.empty((4, lx, lz), dtype=torch.float32, device=DEV)
     abi.lbm_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags), gh, fin, fout, m32)
-    out_f = torch.empty((37, lx, lz), dtype=torch.float32, device=DEV)
-    abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | abi.ADJ_F32), gh, m32, _t(lam), out_f)
-    out_d = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
-    abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags), gh, m32, _t(lam.astype(np.float64)),
-                         out_d)
-    got = out_f.cpu().numpy().astype(np.float64)
-    arith = _rel_max(got, out_d.cpu().numpy())
+    out_f = abi.empty_populations(abi.make_params(lx, lz, p.tau, p.g), torch.float32)
+    abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | abi.ADJ_F32), gh, m32, _pop(abi, lam),
+                         out_f)
+    out_d = abi.empty_populations(abi.make_params(lx, lz, p.tau, p.g), torch.float64)
+    abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags), gh, m32,
+                         _pop(abi, lam.astype(np.float64)), out_d)
+    got = _np(abi, lx, lz, out_f).astype(np.float64)
+    arith = _rel_max(got, _np(abi, lx, lz, out_d))
     err = _rel_max(got, want)
     print(f"all-float adjoint step ({wall}): float arithmetic {arith:.2e} of max "
           f"({arith / 2.0 ** -24:.1f} roundings), vs oracle {err:.2e}")

@@ -35,10 +35,8 @@ def test_profiles_parity(abi, state, prec):
     if prec == "f32dev":
         d = (f - w[:, None, None]).astype(np.float32)
         f = d.astype(np.float64) + w[:, None, None]          # the state the GPU sees
-        buf = torch.as_tensor(np.ascontiguousarray(d), device=DEV)
-    else:
-        buf = torch.as_tensor(np.ascontiguousarray(f), device=DEV)
     params = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g, abi.F64 if prec == "f64" else abi.F32_DEV)
+    buf = abi.to_tiled(params, d if prec == "f32dev" else f)
     prof = torch.empty((4, wl.lz), dtype=torch.float64, device=DEV)
     scratch = torch.empty(abi.lbm_scratch_bytes(params), dtype=torch.uint8, device=DEV)
     abi.lbm_profiles(params, buf, prof, scratch)
@@ -66,10 +64,10 @@ def test_paper_geometry_init_and_objective(abi, single):
     from paper_1405_1253_amd.runtime import Lattice
     lat = Lattice(lx, lz, tau, g)
     lat.init_rt3(t_d, t_m, t_u, 4.0, m.k, m.phase, m.amp, z_lo, z_hi)
-    assert np.max(np.abs(lat.state.cpu().numpy() / f0 - 1)) <= 1e-13
+    assert np.max(np.abs(lat.state_soa().cpu().numpy() / f0 - 1)) <= 1e-13
     assert np.max(np.abs(lat.ghost.cpu().numpy() / ghost - 1)) <= 1e-13
     lat.step(5)
-    assert np.max(np.abs(lat.state.cpu().numpy() / f5 - 1)) <= 1e-12
+    assert np.max(np.abs(lat.state_soa().cpu().numpy() / f5 - 1)) <= 1e-12
     lat.diag_desc = abi.RT3Desc(t_d, 1.0, t_u, 4.0)
     j = lat.objective().cpu().numpy()
     Jo, ke, L = O.objective(f5, p, t_u, 1.0, t_d)

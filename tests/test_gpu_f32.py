@@ -85,8 +85,8 @@ def test_f32_propagate_keeps_deviation_bits(abi):
     d = (W.random_populations(9, lx, lz) - 1.0).astype(np.float32) * 1e-3
     ghost = (W.random_ghost(10) - 2.5).astype(np.float32) * 1e-3
     params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F32_DEV, abi.NO_COLLIDE)
-    fin = torch.as_tensor(d, device=DEV)
+    fin = abi.to_tiled(params, d)
     fout = torch.empty_like(fin)
     abi.lbm_step(params, torch.as_tensor(ghost, device=DEV), fin, fout)
     want = O.pull(d, ghost, O.Params(lx, lz, 0.7, 1e-4, no_collide=True))
-    assert np.array_equal(fout.cpu().numpy(), want)
+    assert np.array_equal(abi.to_soa(params, fout).cpu().numpy(), want)

@@ -41,11 +41,13 @@ def test_fullsize_sampled_columns(name, tol):
     ghost_gpu = lat.ghost.to(torch.float64).cpu().numpy()
     w = None
     if wl.precision == "f32dev":
-        from paper_1405_1253_amd import abi
-        w = abi.lbm_lattice()[1]
+        from paper_1405_1253_amd import abi as _abi
+        w = _abi.lbm_lattice()[1]
+
+    from paper_1405_1253_amd import abi
 
     def column(x):
-        c = lat.state[:, x, :].to(torch.float64).cpu().numpy()
+        c = abi.column(lat.params, lat.state, x).to(torch.float64).cpu().numpy()
         return c + w[:, None] if w is not None else c
 
     got = {0: {x: column(x) for x in SAMPLES}}
@@ -82,7 +84,8 @@ def test_fullsize_bitwise_reproducible():
     for _ in range(2):
         lat = Lattice.from_workload(wl)
         lat.step(20)
-        cols.append(lat.state[:, ::511, ::97].cpu().numpy())
+        from paper_1405_1253_amd import abi
+        cols.append(abi.tiled_view(lat.params, lat.state)[:, ::511, :, ::97].cpu().numpy())
         del lat
         torch.cuda.empty_cache()
     assert np.array_equal(cols[0], cols[1])

@@ -71,10 +71,10 @@ def test_streaming_in_place(abi, prec, mode, lx, lz):
     ghost = W.random_ghost(600 + lz).astype(dt)
     flags = abi.NO_COLLIDE | {"dirichlet": 0, "diffuse": abi.WALL_DIFFUSE, "periodic": abi.PERIODIC_Z}[mode]
     params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F64 if prec == "f64" else abi.F32_DEV, flags)
-    f0, gh = torch.as_tensor(f, device=DEV), torch.as_tensor(ghost, device=DEV)
+    f0, gh = abi.to_tiled(params, f), torch.as_tensor(ghost, device=DEV)
     one, _ = _in_place(abi, params, gh, f0, 1)
     pulled, _ = _two_buffer(abi, params, gh, f0, 1)
-    got, g = one.cpu().numpy(), pulled.cpu().numpy()
+    got, g = abi.to_soa(params, one).cpu().numpy(), abi.to_soa(params, pulled).cpu().numpy()
     E, opp = lattice()[0], _opp()
     want = np.empty_like(got)
     for l in range(37):
@@ -90,13 +90,13 @@ def test_streaming_in_place(abi, prec, mode, lx, lz):
     assert np.array_equal(got, want)
     two, _ = _in_place(abi, params, gh, f0, 2)
     ref, _ = _two_buffer(abi, params, gh, f0, 2)
-    assert torch.equal(two, ref)
+    assert torch.equal(abi.to_soa(params, two), abi.to_soa(params, ref))
 
 
 def _init(abi, params, seed, width=4.0, nmodes=16):
     m = W.draw_modes(seed, nmodes)
     dt = torch.float64 if params.precision == abi.F64 else torch.float32
-    f = torch.empty((37, params.lx, params.lz), dtype=dt, device=DEV)
+    f = abi.empty_populations(params, dt)
     gh = torch.empty((2, 3, 37), dtype=dt, device=DEV)
     abi.lbm_init_rt3(params, abi.RT3Desc(1.05, 1.0, 0.95, width, m.k, m.phase),
                      torch.as_tensor(m.amp, device=DEV), f, gh)
@@ -114,7 +114,7 @@ def test_in_place_equals_two_buffers(abi, prec, wall):
     for steps in (2, 20):
         a, ma = _in_place(abi, params, gh, f0, steps, mom=True)
         b, mb = _two_buffer(abi, params, gh, f0, steps, mom=True)
-        a, b = a.double(), b.double()
+        a, b = abi.to_soa(params, a).double(), abi.to_soa(params, b).double()
         if prec == "f64":
             err = float(((a - b).abs() / b.abs()).max())
             bar = 1e-13
@@ -141,7 +141,7 @@ def test_in_place_parity_with_oracle_ragged_and_tiny(abi):
         f_o, ghost_o = O.init_rt3(p, O.RT3(1.05, 1.0, 0.95, width, m.k, m.phase), m.amp)
         want = O.run(f_o, ghost_o, p, steps)
         got, _ = _in_place(abi, params, gh, f0, steps)
-        err = float(np.max(np.abs(got.cpu().numpy() - want) / want))
+        err = float(np.max(np.abs(abi.to_soa(params, got).cpu().numpy() - want) / want))
         assert err <= 1e-12, (lx, lz, wall, err)
 
 
@@ -159,7 +159,8 @@ def test_lattice_in_place_runtime(abi):
         lat.sums()
     lat.step(1)
     ref.step(4)
-    assert float(((lat.state - ref.state).abs() / ref.state.abs()).max()) <= 1e-13
+    a, b = lat.state_soa(), ref.state_soa()
+    assert float(((a - b).abs() / b.abs()).max()) <= 1e-13
     a, b = lat.sums(), ref.sums()              # mass, momentum (~0 in x), energy
     assert float((a - b).abs().max()) <= 1e-12 * float(b[0])
 
@@ -193,9 +194,10 @@ def test_largest_lattice_single_buffer(abi):
     lat = Lattice.from_workload(wl, modes=m)
     assert lat.inplace and len(lat.buf) == 1
     samples = (0, 8191, 16383)
-    got = {0: {x: lat.state[:, x, :].cpu().numpy() for x in samples}}
+    got = {0: {x: abi.column(lat.params, lat.state, x).cpu().numpy() for x in samples}}
     lat.step(2)
-    got[2] = {x: lat.state[:, x, :].cpu().numpy() for x in samples}
+    got[2] = {x: abi.column(lat.params, lat.state, x).cpu().numpy() for x in samples}
+    assert wl.lz % abi.TILE == 0          # no padding rows: the raw sum is the lattice's
     mass, total = lat.sums()[0].item(), lat.state.sum().item()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()

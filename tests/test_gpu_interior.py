@@ -74,12 +74,12 @@ def test_propagate_bit_exact_interior(abi, lx, lz, prec, periodic):
     ghost = W.random_ghost(400 + lz).astype(np_dt)
     flags = abi.NO_COLLIDE | (abi.PERIODIC_Z if periodic else 0)
     params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F64 if prec == "f64" else abi.F32_DEV, flags)
-    fin = _t(f)
+    fin = abi.to_tiled(params, f)
     fout = torch.full_like(fin, float("nan"))
     abi.lbm_step(params, _t(ghost), fin, fout)
     torch.cuda.synchronize()
     want = O.pull(f, ghost, O.Params(lx, lz, 0.7, 1e-4, periodic_z=periodic, no_collide=True))
-    assert np.array_equal(fout.cpu().numpy(), want)
+    assert np.array_equal(abi.to_soa(params, fout).cpu().numpy(), want)
 
 
 # ---------------------------------------------------------------------------
@@ -102,7 +102,7 @@ def interior_run():
 def _gpu_run(abi, p, m, prec, steps, flags=0):
     dt = torch.float64 if prec == "f64" else torch.float32
     params = abi.make_params(p.lx, p.lz, p.tau, p.g, abi.F64 if prec == "f64" else abi.F32_DEV, flags)
-    fa = torch.empty((37, p.lx, p.lz), dtype=dt, device=DEV)
+    fa = abi.empty_populations(params, dt)
     gh = torch.empty((2, 3, 37), dtype=dt, device=DEV)
     abi.lbm_init_rt3(params, abi.RT3Desc(1.05, 1.0, 0.95, 4.0, m.k, m.phase), _t(m.amp * 4), fa, gh)
     fb = torch.empty_like(fa)
@@ -111,7 +111,7 @@ def _gpu_run(abi, p, m, prec, steps, flags=0):
         abi.lbm_step(params, gh, fa, fb)
         fa, fb = fb, fa
         if s in (1, steps):
-            out.append(fa.double().cpu().numpy())
+            out.append(abi.to_soa(params, fa).double().cpu().numpy())
     return out
 
 
@@ -166,12 +166,12 @@ def test_adjoint_step_parity_interior(abi, lx, lz, mode):
     lam = np.random.default_rng(lx + 7 * lz).standard_normal((37, lx, lz))
     want = A.step_vjp(lam, f, ghost, p)
     params = abi.make_params(lx, lz, p.tau, p.g, flags=flags)
-    fin, gh = _t(f), _t(ghost)
+    fin, gh = abi.to_tiled(params, f), _t(ghost)
     mom = torch.empty((4, lx, lz), dtype=torch.float64, device=DEV)
     abi.lbm_step(params, gh, fin, torch.empty_like(fin), mom)
     lam_out = torch.full_like(fin, float("nan"))
-    abi.lbm_adjoint_step(params, gh, mom, _t(lam), lam_out)
-    got = lam_out.cpu().numpy()
+    abi.lbm_adjoint_step(params, gh, mom, abi.to_tiled(params, lam), lam_out)
+    got = abi.to_soa(params, lam_out).cpu().numpy()
     assert np.isfinite(got).all()
     err = _rel_max(got, want)
     print(f"adjoint {mode} {lx}x{lz}: {err:.2e} of max")
@@ -192,33 +192,34 @@ def test_adjoint_step_float_forms_interior(abi, lx, lz, mode, form):
     p, f, ghost, flags = _adj_case(abi, lx, lz, mode, 13 * lx + lz)
     lam = np.random.default_rng(3 * lx + lz).standard_normal((37, lx, lz)).astype(np.float32)
     want = A.step_vjp(lam.astype(np.float64), f, ghost, p)
-    fin, gh = _t(f), _t(ghost)
+    pp = abi.make_params(lx, lz, p.tau, p.g)   # lattice shape for the layout conversions
+    fin, gh = abi.to_tiled(pp, f), _t(ghost)
     mflags = abi.MOM_F32 if form != "float_buffers" else 0
     mdt = torch.float32 if mflags else torch.float64
     mom = torch.empty((4, lx, lz), dtype=mdt, device=DEV)
     abi.lbm_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | mflags), gh, fin, torch.empty_like(fin), mom)
     if form == "float_moments":
-        out = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
+        out = abi.empty_populations(pp, torch.float64)
         abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | mflags), gh, mom,
-                             _t(lam.astype(np.float64)), out)
-        err = _rel_max(out.cpu().numpy(), want)
+                             abi.to_tiled(pp, lam.astype(np.float64)), out)
+        err = _rel_max(abi.to_soa(pp, out).cpu().numpy(), want)
         bound = 1e-6
     else:
-        out = torch.empty((37, lx, lz), dtype=torch.float32, device=DEV)
+        out = abi.empty_populations(pp, torch.float32)
         abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | mflags | abi.ADJ_F32), gh, mom,
-                             _t(lam), out)
-        got = out.cpu().numpy().astype(np.float64)
+                             abi.to_tiled(pp, lam), out)
+        got = abi.to_soa(pp, out).cpu().numpy().astype(np.float64)
         err = _rel_max(got, want)
         if form == "float_buffers":
             bound = 2.0 ** -23 if not mode.startswith("diffuse") else 3 * 2.0 ** -24
         else:
-            ref = torch.empty((37, lx, lz), dtype=torch.float64, device=DEV)
+            ref = abi.empty_populations(pp, torch.float64)
             abi.lbm_adjoint_step(abi.make_params(lx, lz, p.tau, p.g, flags=flags | mflags), gh, mom,
-                                 _t(lam.astype(np.float64)), ref)
-            arith = _rel_max(got, ref.cpu().numpy())
+                                 abi.to_tiled(pp, lam.astype(np.float64)), ref)
+            arith = _rel_max(got, abi.to_soa(pp, ref).cpu().numpy())
             print(f"all-float {mode} {lx}x{lz}: float arithmetic {arith / 2.0 ** -24:.1f} roundings")
             assert arith <= 32 * 2.0 ** -24
             bound = 32 * 2.0 ** -24 + 1e-6
-    assert np.isfinite(out.cpu().numpy()).all()
+    assert np.isfinite(abi.to_soa(pp, out).cpu().numpy()).all()
     print(f"adjoint {form} {mode} {lx}x{lz}: {err:.2e} of max (bar {bound:.1e})")
     assert err <= bound

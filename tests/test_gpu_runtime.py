@@ -22,11 +22,11 @@ def test_checkpoint_restore_is_bitwise(tmp_path, name, precision):
     path = tmp_path / "ckpt.pt"
     lat.save(path)
     lat.step(15)
-    straight = lat.state.cpu().numpy()
+    straight = lat.state_soa().cpu().numpy()
     back = Lattice.load(path)
     assert back.steps_done == 10
     back.step(15)
-    assert np.array_equal(back.state.cpu().numpy(), straight)
+    assert np.array_equal(back.state_soa().cpu().numpy(), straight)
 
 
 def test_nonfinite_state_is_reported():
@@ -35,7 +35,9 @@ def test_nonfinite_state_is_reported():
     lat = Lattice.from_workload(wl)
     lat.step(3)
     lat.sums()                                   # finite: no error
-    lat.state[5, 17, 100] = float("nan")         # forced from the host
+    f = lat.state_soa()
+    f[5, 17, 100] = float("nan")                 # forced from the host
+    lat.set_state(f)
     lat.step(2)
     with pytest.raises(FloatingPointError):
         lat.sums()

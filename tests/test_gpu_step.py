@@ -36,8 +36,7 @@ def _oracle_setup(lx, lz, tau, g, seed, nmodes=16, t=(1.05, 1.0, 0.95), width=4.
 
 
 def _gpu_init(abi, lat_p, m, t=(1.05, 1.0, 0.95), width=4.0, dtype=torch.float64):
-    lx, lz = lat_p.lx, lat_p.lz
-    f = torch.empty((37, lx, lz), dtype=dtype, device=DEV)
+    f = abi.empty_populations(lat_p, dtype)
     ghost = torch.empty((2, 3, 37), dtype=dtype, device=DEV)
     amp = torch.as_tensor(m.amp, device=DEV)
     abi.lbm_init_rt3(lat_p, abi.RT3Desc(t[0], t[1], t[2], width, m.k, m.phase), amp, f, ghost)
@@ -63,12 +62,12 @@ def test_propagate_bit_exact(abi, lx, lz, prec, periodic):
     ghost = W.random_ghost(200 + lz).astype(np_dt)
     flags = abi.NO_COLLIDE | (abi.PERIODIC_Z if periodic else 0)
     params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F64 if prec == "f64" else abi.F32_DEV, flags)
-    fin = torch.as_tensor(f, device=DEV)
+    fin = abi.to_tiled(params, f)
     fout = torch.full_like(fin, float("nan"))
     abi.lbm_step(params, torch.as_tensor(ghost, device=DEV), fin, fout)
     torch.cuda.synchronize()
     want = O.pull(f, ghost, O.Params(lx, lz, 0.7, 1e-4, periodic_z=periodic, no_collide=True))
-    assert np.array_equal(fout.cpu().numpy(), want)
+    assert np.array_equal(abi.to_soa(params, fout).cpu().numpy(), want)
 
 
 # ---------------------------------------------------------------------------
@@ -89,7 +88,7 @@ def test_init_parity_f64(abi, c1_oracle):
     wl, m, p, desc, f0, ghost, _, _ = c1_oracle
     params = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g)
     f, gh = _gpu_init(abi, params, m)
-    assert _rel(f.cpu().numpy(), f0) <= 1e-13
+    assert _rel(abi.to_soa(params, f).cpu().numpy(), f0) <= 1e-13
     assert _rel(gh.cpu().numpy(), ghost) <= 1e-13
 
 
@@ -99,11 +98,11 @@ def test_step_parity_f64_1_and_100_steps(abi, c1_oracle):
     fa, gh = _gpu_init(abi, params, m)
     fb = torch.empty_like(fa)
     abi.lbm_step(params, gh, fa, fb)
-    e1 = _rel(fb.cpu().numpy(), f1)
+    e1 = _rel(abi.to_soa(params, fb).cpu().numpy(), f1)
     for _ in range(99):
         abi.lbm_step(params, gh, fb, fa)
         fa, fb = fb, fa
-    e100 = _rel(fb.cpu().numpy(), f100)
+    e100 = _rel(abi.to_soa(params, fb).cpu().numpy(), f100)
     print(f"FP64 max rel err: 1 step {e1:.3e}, 100 steps {e100:.3e}")
     assert e1 <= 1e-12 and e100 <= 1e-12
 
@@ -119,7 +118,7 @@ def test_step_parity_f64_ragged(abi):
     for _ in range(steps):
         abi.lbm_step(params, gh, fa, fb)
         fa, fb = fb, fa
-    assert _rel(fa.cpu().numpy(), want) <= 1e-12
+    assert _rel(abi.to_soa(params, fa).cpu().numpy(), want) <= 1e-12
 
 
 def test_step_parity_tiny_lattices(abi):
@@ -135,13 +134,13 @@ def test_step_parity_tiny_lattices(abi):
         for _ in range(3):
             abi.lbm_step(params, gh, fa, fb)
             fa, fb = fb, fa
-        assert _rel(fa.cpu().numpy(), want) <= 1e-12, (lx, lz)
+        assert _rel(abi.to_soa(params, fa).cpu().numpy(), want) <= 1e-12, (lx, lz)
 
 
 def test_moments_parity(abi, c1_oracle):
     wl, m, p, desc, f0, ghost, f1, f100 = c1_oracle
     params = abi.make_params(wl.lx, wl.lz, wl.tau, wl.g)
-    f = torch.as_tensor(np.ascontiguousarray(f100), device=DEV)
+    f = abi.to_tiled(params, f100)
     fields = torch.empty((4, wl.lx, wl.lz), dtype=torch.float64, device=DEV)
     tbar = torch.empty(wl.lz, dtype=torch.float64, device=DEV)
     sums = torch.empty(4, dtype=torch.float64, device=DEV)
@@ -189,13 +188,13 @@ def test_bitwise_reproducible(abi):
         sums = torch.empty(4, dtype=torch.float64, device=DEV)
         scratch = torch.empty(abi.lbm_scratch_bytes(params), dtype=torch.uint8, device=DEV)
         abi.lbm_moments(params, fa, sums=sums, scratch=scratch)
-        outs.append((fa.cpu().numpy(), sums.cpu().numpy()))
+        outs.append((abi.to_soa(params, fa).cpu().numpy(), sums.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
 def test_runtime_errors(abi):
     params = abi.make_params(16, 16, 0.7, 1e-4)
-    f = torch.zeros((37, 16, 16), dtype=torch.float64, device=DEV)
+    f = abi.empty_populations(params, torch.float64).zero_()
     gh = torch.zeros((2, 3, 37), dtype=torch.float64, device=DEV)
     with pytest.raises(abi.LbmError, match="EALIAS"):
         abi.lbm_step(params, gh, f, f)
@@ -217,7 +216,7 @@ def test_gpu_x_uniform_state_stays_x_uniform(abi):
     for _ in range(200):
         abi.lbm_step(params, gh, fa, fb)
         fa, fb = fb, fa
-    f = fa.cpu().numpy()
+    f = abi.to_soa(params, fa).cpu().numpy()
     assert all(np.array_equal(f[:, x], f[:, 0]) for x in range(lx))
 
 
@@ -229,7 +228,7 @@ def test_gpu_periodic_momentum_and_mass(abi):
     T = rng.uniform(0.95, 1.05, (lx, lz))
     f0 = O.equilibrium(rho, u, T)
     params = abi.make_params(lx, lz, 0.9, g, flags=abi.PERIODIC_Z)
-    fa = torch.as_tensor(np.ascontiguousarray(f0), device=DEV)
+    fa = abi.to_tiled(params, f0)
     fb = torch.empty_like(fa)
     sums = torch.empty(4, dtype=torch.float64, device=DEV)
     scratch = torch.empty(abi.lbm_scratch_bytes(params), dtype=torch.uint8, device=DEV)

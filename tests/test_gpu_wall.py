@@ -39,7 +39,7 @@ def _setup(lx, lz, tau, g, seed, nmodes=16, width=4.0):
 
 
 def _gpu_init(abi, params, m, width=4.0):
-    f = torch.empty((37, params.lx, params.lz), dtype=torch.float64, device=DEV)
+    f = abi.empty_populations(params, torch.float64)
     gh = torch.empty((2, 3, 37), dtype=torch.float64, device=DEV)
     desc = abi.RT3Desc(1.05, 1.0, 0.95, width, m.k, m.phase)
     abi.lbm_init_rt3(params, desc, torch.as_tensor(m.amp, device=DEV), f, gh)
@@ -51,10 +51,10 @@ def test_diffuse_streaming_f64(abi, lx, lz):
     f = W.random_populations(300 + lx, lx, lz)
     ghost = W.random_ghost(400 + lz)
     params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F64, abi.NO_COLLIDE | abi.WALL_DIFFUSE)
-    fin = torch.as_tensor(f, device=DEV)
+    fin = abi.to_tiled(params, f)
     fout = torch.full_like(fin, float("nan"))
     abi.lbm_step(params, torch.as_tensor(ghost, device=DEV), fin, fout)
-    got = fout.cpu().numpy()
+    got = abi.to_soa(params, fout).cpu().numpy()
     want = O.pull(f, ghost, O.Params(lx, lz, 0.7, 1e-4, no_collide=True, wall="diffuse"))
     assert np.abs(got - want).max() <= 4 * EPS * np.abs(want).max()
     inner = slice(3, max(lz - 3, 3))
@@ -69,8 +69,9 @@ def test_diffuse_streaming_f32(abi):
     d = (W.random_populations(31, lx, lz) - w[:, None, None]).astype(np.float32)
     dg = (W.random_ghost(32) - w[None, None, :]).astype(np.float32)
     params = abi.make_params(lx, lz, 0.7, 1e-4, abi.F32_DEV, abi.NO_COLLIDE | abi.WALL_DIFFUSE)
-    fout = torch.full((37, lx, lz), float("nan"), dtype=torch.float32, device=DEV)
-    abi.lbm_step(params, torch.as_tensor(dg, device=DEV), torch.as_tensor(d, device=DEV), fout)
+    fout = abi.empty_populations(params, torch.float32).fill_(float("nan"))
+    abi.lbm_step(params, torch.as_tensor(dg, device=DEV), abi.to_tiled(params, d), fout)
+    fout = abi.to_soa(params, fout)
     got = fout.cpu().numpy().astype(np.float64) + w[:, None, None]
     f = d.astype(np.float64) + w[:, None, None]
     want = O.pull(f, dg.astype(np.float64) + w[None, None, :],
@@ -96,11 +97,11 @@ def test_diffuse_step_parity_f64_1_and_100_steps(abi, c1_diffuse):
     fa, gh = _gpu_init(abi, params, m)
     fb = torch.empty_like(fa)
     abi.lbm_step(params, gh, fa, fb)
-    e1 = _rel(fb.cpu().numpy(), f1)
+    e1 = _rel(abi.to_soa(params, fb).cpu().numpy(), f1)
     for _ in range(99):
         abi.lbm_step(params, gh, fb, fa)
         fa, fb = fb, fa
-    e100 = _rel(fb.cpu().numpy(), f100)
+    e100 = _rel(abi.to_soa(params, fb).cpu().numpy(), f100)
     print(f"diffuse wall, FP64 max rel err: 1 step {e1:.3e}, 100 steps {e100:.3e}")
     assert e1 <= 1e-12 and e100 <= 1e-12
 
@@ -116,7 +117,7 @@ def test_diffuse_step_parity_ragged_and_tiny(abi):
         for _ in range(steps):
             abi.lbm_step(params, gh, fa, fb)
             fa, fb = fb, fa
-        assert _rel(fa.cpu().numpy(), want) <= 1e-12, (lx, lz)
+        assert _rel(abi.to_soa(params, fa).cpu().numpy(), want) <= 1e-12, (lx, lz)
 
 
 def test_diffuse_step_f32_error_bound(abi, c1_diffuse):
@@ -176,7 +177,7 @@ def test_diffuse_fullsize_sampled_columns(abi):
     got = {}
     for n in (1, 2):
         lat.step(1)
-        got[n] = {x: lat.state[:, x, :].cpu().numpy() for x in samples}
+        got[n] = {x: abi.column(lat.params, lat.state, x).cpu().numpy() for x in samples}
     del lat
     torch.cuda.empty_cache()
     worst = 0.0

@@ -29,7 +29,7 @@ def _state(abi, lx, lz, prec, seed, steps=3):
     dt = torch.float64 if prec == "f64" else torch.float32
     params = abi.make_params(lx, lz, 0.7, 2e-4, abi.F64 if prec == "f64" else abi.F32_DEV)
     m = W.draw_modes(seed, 6)
-    f = torch.empty((37, lx, lz), dtype=dt, device=DEV)
+    f = abi.empty_populations(params, dt)
     gh = torch.empty((2, 3, 37), dtype=dt, device=DEV)
     abi.lbm_init_rt3(params, abi.RT3Desc(1.05, 1.0, 0.95, 4.0, m.k, m.phase),
                      torch.as_tensor(m.amp * 3, device=DEV), f, gh)
@@ -61,8 +61,8 @@ def test_noalloc_matches_moments_on_two_calls(abi):
         assert torch.equal(tbar2, tbar), (lx, lz)
         assert torch.equal(sums2, sums), (lx, lz)
         # the mass is the plain sum of the populations (independent of both)
-        full = f.double() if prec == "f64" else f.double() + torch.as_tensor(
-            abi.lbm_lattice()[1], device=DEV)[:, None, None]
+        soa = abi.to_soa(params, f).double()
+        full = soa if prec == "f64" else soa + torch.as_tensor(abi.lbm_lattice()[1], device=DEV)[:, None, None]
         assert abs(sums2[0].item() / full.sum().item() - 1) <= 1e-12
 
 
