@@ -172,18 +172,24 @@ def pull_transpose(G, p, ghost=None):
     return out
 
 
-def step_vjp(lam, f_prev, ghost, p):
-    """lam_{t-1} = (d step / d f*_{t-1})^T lam_t for the step from f_prev."""
-    g = lbm.pull(f_prev, ghost, p)
+def collide_vjp(lam, g, p):
+    """(d collide / d g)^T lam: dJ/dg for the pre-collision populations g of
+    a step, given lam = dJ/df* of its output (eq. LBE)."""
     if p.no_collide:
-        return pull_transpose(lam, p, ghost)
+        return lam
     om = 1.0 / p.tau
     rho, u, T = lbm.moments(g)
     v, Teq = lbm.shifted_state(u, T, p)
     g_rho, g_v, g_T = equilibrium_vjp(lam, rho, v, Teq)
     # v = u + tau g_vec and Teq = T + const: d/du = d/dv, d/dT = d/dTeq
-    G = (1.0 - om) * lam + om * moments_vjp(g, g_rho, g_v, g_T)
-    return pull_transpose(G, p, ghost)
+    return (1.0 - om) * lam + om * moments_vjp(g, g_rho, g_v, g_T)
+
+
+def step_vjp(lam, f_prev, ghost, p):
+    """lam_{t-1} = (d step / d f*_{t-1})^T lam_t for the step from f_prev:
+    the streaming transpose of the collision transpose."""
+    g = lbm.pull(f_prev, ghost, p)
+    return pull_transpose(collide_vjp(lam, g, p), p, ghost)
 
 
 def objective_vjp(f, p, Tu, Tm, Td, wk=1.0, wl=1.0):
