@@ -246,17 +246,25 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
         t_plain.append(timed(lambda: plain_forward(wl.steps))[0])
     plain = sum(t_plain) / len(t_plain)
 
-    # the adjoint step alone, on the rollout's buffers
+    # the adjoint step alone, on the rollout's buffers: the gather form the
+    # rollout uses, and the push form for comparison
     mom = r.kept[0] if r.keep else r.segbuf[0]
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    abi.lbm_adjoint_step(r.params, r.ghost, mom, r.lam[0], r.lam[1])
-    e0.record(stream)
-    for i in range(20):
-        abi.lbm_adjoint_step(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_adj = e0.elapsed_time(e1) / 20 / 1e3
+
+    def adj_time(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn(0)
+        e0.record(stream)
+        for i in range(20):
+            fn(i)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 20 / 1e3
+
+    t_push = adj_time(lambda i: abi.lbm_adjoint_step(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2]))
+    t_adj = (t_push if r.form == "push" else
+             adj_time(lambda i: abi.lbm_adjoint_gather(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2],
+                                                       r.scratch)))
     site_bytes = 2 * abi.Q * r.lam[0].element_size() + 4 * mom.element_size()
     adj_gbs = site_bytes * wl.lx * wl.lz / t_adj / 1e9
     out = {"workload": name, "steps": wl.steps, "plain_forward_s": [round(t, 4) for t in t_plain],
@@ -266,7 +274,8 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
            "recomputed_steps": r.recomputed_steps, "moments_kept": r.keep,
            "ckpt_every": r.ckpt_every, "state_checkpoints": len(r.ckpt),
            "moments_dtype": str(mom.dtype).replace("torch.", ""),
-           "adjoint_step_ms": round(t_adj * 1e3, 4),
+           "adjoint_form": r.form, "adjoint_step_ms": round(t_adj * 1e3, 4),
+           "adjoint_push_step_ms": round(t_push * 1e3, 4),
            "adjoint_step_over_forward_step": round(t_adj / (plain / wl.steps), 3),
            "adjoint_hbm_gbs": round(adj_gbs, 1), "adjoint_frac": round(adj_gbs / HBM_PEAK_GBS, 4),
            "adjoint_traffic": (measured_adjoint_traffic(name)
@@ -338,8 +347,9 @@ def copy_calibration(nbytes=4 << 30, reps=3):
 
 def adjoint_counter_run(launches=6):
     """A short sequence for the HBM counters of the adjoint step: at the
-    2048 x 6144 float rollout's shape, ``launches`` all-float adjoint steps
-    (float buffers and moments) and then ``launches`` streaming-only ones."""
+    2048 x 6144 float rollout's shape, ``launches`` all-float adjoint steps in
+    gather form (lbm_adjoint_gather: float buffers and moments), then
+    ``launches`` streaming-only ones (S^T alone)."""
     import torch
     from paper_1405_1253_amd import abi
     from paper_1405_1253_amd.workload import WORKLOADS, draw_modes
@@ -359,9 +369,9 @@ def adjoint_counter_run(launches=6):
     gen = torch.Generator(device="cuda").manual_seed(wl.seed)
     lam = [torch.randn(shape, dtype=torch.float32, device="cuda", generator=gen), torch.empty_like(f)]
     for i in range(launches):
-        abi.lbm_adjoint_step(p_adj, gh, mom, lam[i % 2], lam[1 - i % 2])
+        abi.lbm_adjoint_gather(p_adj, gh, mom, lam[i % 2], lam[1 - i % 2])
     for i in range(launches):
-        abi.lbm_adjoint_step(p_str, gh, None, lam[i % 2], lam[1 - i % 2])
+        abi.lbm_adjoint_gather(p_str, gh, None, lam[i % 2], lam[1 - i % 2])
     torch.cuda.synchronize()
     print(json.dumps({"adjoint_counter_run": wl.name, "sites": wl.lx * wl.lz,
                       "launches_all_float": launches, "launches_streaming_only": launches}), flush=True)

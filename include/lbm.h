@@ -252,7 +252,8 @@ int lbm_unpack(const lbm_params *params, const void *tiled, void *soa, int elt_b
 /*
  * lbm_scratch_bytes -- size of the scratch buffer that lbm_moments,
  * lbm_profiles, lbm_objective, lbm_init_rt3_vjp and (with diffuse walls)
- * lbm_step_inplace need (bytes).  Returns 0 for invalid params.
+ * lbm_step_inplace and lbm_adjoint_gather need (bytes).  Returns 0 for
+ * invalid params.
  */
 size_t lbm_scratch_bytes(const lbm_params *params);
 
@@ -378,6 +379,47 @@ int lbm_objective(const lbm_params *params, const lbm_rt3_desc *desc, const void
  */
 int lbm_adjoint_step(const lbm_params *params, const void *ghost, const double *moments,
                      const void *lam_in, void *lam_out, lbm_stream_t stream);
+
+/*
+ * lbm_adjoint_collide, lbm_adjoint_gather -- the adjoint of a chain of steps
+ * in gather form.
+ *
+ * A step is f_out = C(S f_in) with S the streaming and wall step (a pull)
+ * and C the per-site collision of Sec. III.A (eq. LBE), so a chain of N
+ * steps has the adjoint lam_0 = S^T C_1^T S^T C_2^T ... S^T C_N^T lam_N.
+ * lbm_adjoint_step applies S^T C_t^T per call with S^T as a scatter.
+ * Grouped around mu_t = C_t^T lam_t (dJ with respect to the pre-collision
+ * populations g of step t), the chain is
+ *     mu_N = C_N^T lam_N                       lbm_adjoint_collide (moments of step N)
+ *     mu_{t-1} = C_{t-1}^T S^T mu_t            lbm_adjoint_gather (moments of step t-1)
+ *     lam_0 = S^T mu_1                         lbm_adjoint_gather with LBM_NO_COLLIDE
+ * and S^T becomes a gather: (S^T mu)_l(y) = mu_l(y + e_l) (x periodic) where
+ * y + e_l lies inside the walls; beyond a wall it is 0 for the Dirichlet
+ * wall and, with LBM_WALL_DIFFUSE, A(s) = sum_m c_m mu_m(s + e_m) / sum_m c_m
+ * for the ghost site s = y + e_l (the m with s + e_m inside the walls, c_m
+ * = its table row).  C^T at a site is the map of lbm_adjoint_step:
+ *     out_l = (1 - omega) in_l + alpha + beta . xi_l + gamma |xi_l|^2
+ * with (alpha, beta, gamma) from the site's 37 values and its moments.
+ * Every output element is written by its own site (aligned writes); the
+ * chain gives lbm_adjoint_step's results to rounding (the same per-site
+ * arithmetic, contracted into multiply-adds as the compiler chooses).
+ *
+ *   moments  (device) double [4][Lx][Lz] (float with LBM_MOM_F32) of the step
+ *            whose collision is transposed (NULL allowed with LBM_NO_COLLIDE)
+ *   lam, mu_in  (device) population buffers, double (float with LBM_ADJ_F32)
+ *   mu, mu_out  (device) same type, must not overlap the inputs
+ *   ghost    (device) the forward step's wall table; required with
+ *            LBM_WALL_DIFFUSE, otherwise unused
+ *   scratch  (device) with LBM_WALL_DIFFUSE: at least lbm_scratch_bytes
+ *            bytes, overwritten (the ghost sites' sums); otherwise unused
+ * Arithmetic and precision as for lbm_adjoint_step.
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION,
+ * LBM_EHIP.
+ */
+int lbm_adjoint_collide(const lbm_params *params, const double *moments, const void *lam, void *mu,
+                        lbm_stream_t stream);
+int lbm_adjoint_gather(const lbm_params *params, const void *ghost, const double *moments, const void *mu_in,
+                       void *mu_out, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
 
 /*
  * lbm_init_rt3_vjp -- gradient of lbm_init_rt3 with respect to the mode

@@ -91,12 +91,15 @@ def load():
         lib.lbm_objective.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, ctypes.c_double,
                                       ctypes.c_double, _VP, _VP, _VP, ctypes.c_size_t, _VP]
         lib.lbm_adjoint_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
+        lib.lbm_adjoint_collide.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP]
+        lib.lbm_adjoint_gather.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
         lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP]
         lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
         for name in ("lbm_init_rt3", "lbm_step", "lbm_step_inplace", "lbm_moments", "lbm_moments_noalloc",
                      "lbm_lattice", "lbm_objective", "lbm_pack", "lbm_unpack",
-                     "lbm_adjoint_step", "lbm_init_rt3_vjp", "lbm_profiles"):
+                     "lbm_adjoint_step", "lbm_adjoint_collide", "lbm_adjoint_gather", "lbm_init_rt3_vjp",
+                     "lbm_profiles"):
             getattr(lib, name).restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -366,6 +369,27 @@ def lbm_adjoint_step(params, ghost, moments, lam_in, lam_out, stream=None):
     st = load().lbm_adjoint_step(ctypes.byref(params), _ptr(ghost), _ptr(moments), _ptr(lam_in),
                                  _ptr(lam_out), _stream(stream))
     _check(st, "lbm_adjoint_step")
+
+
+def lbm_adjoint_collide(params, moments, lam, mu, stream=None):
+    """mu = C^T lam, the collision adjoint of one step alone (see include/lbm.h)."""
+    _need("moments", moments, _mom_dtype(params), 4 * _sites(params))
+    _need("lam", lam, _lam_dtype(params), population_elems(params))
+    _need("mu", mu, _lam_dtype(params), population_elems(params))
+    st = load().lbm_adjoint_collide(ctypes.byref(params), _ptr(moments), _ptr(lam), _ptr(mu), _stream(stream))
+    _check(st, "lbm_adjoint_collide")
+
+
+def lbm_adjoint_gather(params, ghost, moments, mu_in, mu_out, scratch=None, stream=None):
+    """mu_out = C^T S^T mu_in (S^T alone with NO_COLLIDE), the gather form of
+    the adjoint step (see include/lbm.h)."""
+    _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
+    _need("moments", moments, _mom_dtype(params), 4 * _sites(params))
+    _need("mu_in", mu_in, _lam_dtype(params), population_elems(params))
+    _need("mu_out", mu_out, _lam_dtype(params), population_elems(params))
+    st = load().lbm_adjoint_gather(ctypes.byref(params), _ptr(ghost), _ptr(moments), _ptr(mu_in), _ptr(mu_out),
+                                   _ptr(scratch), _nbytes(scratch), _stream(stream))
+    _check(st, "lbm_adjoint_gather")
 
 
 def lbm_init_rt3_vjp(params, desc, amp, lam0, d_amp, scratch, stream=None):

@@ -147,30 +147,28 @@ __device__ __forceinline__ EqVjp eq_vjp_sums(const LT lam[Q], double vx, double 
 // ---------------------------------------------------------------------------
 // adjoint step
 // ---------------------------------------------------------------------------
-template <bool EDGE, typename L, typename MT>
-__device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0) {
-    // all-float mode (float buffers and float moments): the 15 sums and the
-    // outputs G in float, whose inputs already carry float rounding; the
-    // moments' algebra and (alpha, beta, gamma) stay double
-    using A = typename std::conditional<std::is_same<L, float>::value && std::is_same<MT, float>::value, float,
-                                        double>::type;
-    const L *__restrict__ lam_in = static_cast<const L *>(a.lam_in);
-    L *__restrict__ lam_out = static_cast<L *>(a.lam_out);
-    const size_t N = (size_t)a.lx * (size_t)a.lz;   // moments: [4][Lx][Lz]
-    const int z = z0 + (int)threadIdx.x;
-    if (EDGE && z >= a.lz) return;
-    // lam buffers are tiled (common.h); the block's rows lie in one tile zt
-    const int zt = z0 / TILE, zl = z % TILE;
-    const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
-    const size_t own = ((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)zl;   // (0, x, z)
-    L lam[Q];   // held in the buffer's type (float buffers: half the registers)
-#pragma unroll
-    for (int l = 0; l < Q; ++l) lam[l] = lam_in[own + (size_t)l * TILE];
+// Accumulator type: float in the all-float mode (float buffers and float
+// moments: the 15 sums and the outputs G, whose inputs already carry float
+// rounding); double otherwise.  The moments' algebra and (alpha, beta,
+// gamma) are double in every mode.
+template <typename L, typename MT>
+using AdjAcc = typename std::conditional<std::is_same<L, float>::value && std::is_same<MT, float>::value, float,
+                                         double>::type;
 
-    // G_l = keep lam_l + alpha + beta . xi_l + gamma |xi_l|^2 (NO_COLLIDE: G = lam)
+// Collision adjoint of one site: G_l = keep lam_l + alpha + beta . xi_l +
+// gamma |xi_l|^2 from the site's 37 lam values and pre-collision moments
+// (NO_COLLIDE: G = lam).
+template <typename A>
+struct AdjSite {
+    A gk, ga, gbx, gbz, gg;
+};
+
+template <typename A, typename L, typename MT>
+__device__ __forceinline__ AdjSite<A> adj_site(const AdjointArgs &a, const L lam[Q], int x, int z) {
     double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
     if (!(a.flags & F_NO_COLLIDE)) {
-        // uniform column base + 32-bit per-lane byte offset
+        // moments [4][Lx][Lz]: uniform column base + 32-bit per-lane byte offset
+        const size_t N = (size_t)a.lx * (size_t)a.lz;
         const MT *mcol = static_cast<const MT *>(a.mom) + (size_t)x * (size_t)a.lz;
         const uint32_t moff = (uint32_t)z * (uint32_t)sizeof(MT);
         const double rho = ldg_off(mcol, moff), ux = ldg_off(mcol + N, moff),
@@ -190,23 +188,42 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
         gamma = mu_t * idr;
         keep = 1.0 - om;
     }
+    return AdjSite<A>{(A)keep, (A)alpha, (A)bx, (A)bz, (A)gamma};
+}
 
-    // G_{l} and G_{l+1} (= -e_l) share alpha + gamma |xi|^2 and +-beta . xi_l
-    const A gk = (A)keep, ga = (A)alpha, gbx = (A)bx, gbz = (A)bz, gg = (A)gamma;
-    auto gval = [&](int l) -> A {
-        if (l == 0) return gk * (A)lam[0] + ga;
-        const int p = (l & 1) ? l : l - 1;
-        const A c = ga + gg * (A)XI2_SHELL[SHELL[p]];
-        A bxi;
-        if (EX[p] != 0 && EZ[p] != 0)
-            bxi = (A)EX[p] * gbx + (A)EZ[p] * gbz;
-        else if (EX[p] != 0)
-            bxi = (A)EX[p] * gbx;
-        else
-            bxi = (A)EZ[p] * gbz;
-        const A k = gk * (A)lam[l] + c;
-        return (l & 1) ? k + bxi : k - bxi;
-    };
+// G_l of a site; G_l and G_{l+1} (= -e_l) share alpha + gamma |xi|^2 and +-beta . xi_l
+template <typename A, typename L>
+__device__ __forceinline__ A adj_g(const AdjSite<A> &c, const L lam[Q], int l) {
+    if (l == 0) return c.gk * (A)lam[0] + c.ga;
+    const int p = (l & 1) ? l : l - 1;
+    const A cc = c.ga + c.gg * (A)XI2_SHELL[SHELL[p]];
+    A bxi;
+    if (EX[p] != 0 && EZ[p] != 0)
+        bxi = (A)EX[p] * c.gbx + (A)EZ[p] * c.gbz;
+    else if (EX[p] != 0)
+        bxi = (A)EX[p] * c.gbx;
+    else
+        bxi = (A)EZ[p] * c.gbz;
+    const A k = c.gk * (A)lam[l] + cc;
+    return (l & 1) ? k + bxi : k - bxi;
+}
+
+template <bool EDGE, typename L, typename MT>
+__device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0) {
+    using A = AdjAcc<L, MT>;
+    const L *__restrict__ lam_in = static_cast<const L *>(a.lam_in);
+    L *__restrict__ lam_out = static_cast<L *>(a.lam_out);
+    const int z = z0 + (int)threadIdx.x;
+    if (EDGE && z >= a.lz) return;
+    // lam buffers are tiled (common.h); the block's rows lie in one tile zt
+    const int zt = z0 / TILE, zl = z % TILE;
+    const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
+    const size_t own = ((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)zl;   // (0, x, z)
+    L lam[Q];   // held in the buffer's type (float buffers: half the registers)
+#pragma unroll
+    for (int l = 0; l < Q; ++l) lam[l] = lam_in[own + (size_t)l * TILE];
+    const AdjSite<A> c = adj_site<A, L, MT>(a, lam, x, z);
+    auto gval = [&](int l) -> A { return adj_g<A, L>(c, lam, l); };
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
         const L G = (L)gval(l);
@@ -336,6 +353,152 @@ hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
         else
             hipLaunchKernelGGL((adjoint_wall_kernel<double, double>), wgrid, dim3(BLOCK), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// adjoint step, gather form
+// ---------------------------------------------------------------------------
+// The step is f_out = C(S f_in): S streams (pull, walls), C collides per
+// site.  Its transpose S^T C^T is applied above in push form.  Regrouping a
+// chain of steps, lam_0 = S^T C_1^T S^T C_2^T ... S^T C_N^T lam_N, around
+// mu_t = C_t^T lam_t (the derivative with respect to the pre-collision
+// populations of step t) gives mu_{t-1} = C_{t-1}^T S^T mu_t: the streaming
+// transpose becomes a gather, (S^T mu)_l(y) = mu_l(y + e_l), and the
+// collision adjoint then runs on the gathered values of one site, stored in
+// place (aligned writes).  A backward sweep is C_N^T once (shift = false),
+// then N - 1 gather steps, then S^T alone (F_NO_COLLIDE): every output
+// element is written by its own site, and the shifted accesses are reads,
+// which measured faster than shifted writes on this chip (the Sec. III.B
+// pull/push comparison).
+//
+// Walls: where y + e_l lies beyond a wall, (S^T mu)_l(y) is 0 for the
+// Dirichlet wall and, for the diffuse wall, the ghost site s = y + e_l's sum
+// A(s) = sum_m c_m mu_m(s + e_m) / sum_m c_m over the m pointing back into
+// the lattice (c_m = its table row), formed beforehand by adjoint_gather_wall.
+template <bool EDGE, bool SHIFT, typename L, typename MT>
+__device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x, int z0) {
+    using A = AdjAcc<L, MT>;
+    const L *__restrict__ in = static_cast<const L *>(a.lam_in);
+    L *__restrict__ out = static_cast<L *>(a.lam_out);
+    const int z = z0 + (int)threadIdx.x;
+    if (EDGE && z >= a.lz) return;
+    const int zt = z0 / TILE, zl = z % TILE;
+    const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
+    const size_t own = ((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)zl;   // (0, x, z)
+    const bool periodic = (a.flags & F_PERIODIC_Z) != 0, diffuse = (a.flags & F_WALL_DIFFUSE) != 0;
+    L lam[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+        if (!SHIFT) {
+            lam[l] = in[own + (size_t)l * TILE];
+            continue;
+        }
+        const int xs = EX[l] == 0 ? x : wrap(x + EX[l], a.lx);
+        if (!EDGE) {
+            // row z + e_lz of column x + e_lx: this tile or the one below / above
+            const L *tb = in + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
+            lam[l] = tb[tile_off(l, zl + EZ[l], tstep)];
+            continue;
+        }
+        const int zs = z + EZ[l];
+        if (periodic) {
+            lam[l] = in[pidx(l, xs, wrap(zs, a.lz), a.lx)];
+        } else if (zs >= 0 && zs < a.lz) {
+            // in-range rows as in the interior
+            const L *tb = in + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
+            lam[l] = tb[tile_off(l, zl + EZ[l], tstep)];
+        } else if (diffuse) {   // ghost site (x + e_lx, zs)
+            const int row = zs < 0 ? -zs - 1 : 3 + zs - a.lz;
+            lam[l] = (L)a.wall_a[(size_t)row * (size_t)a.lx + (size_t)xs];
+        } else {
+            lam[l] = L(0);
+        }
+    }
+    const AdjSite<A> c = adj_site<A, L, MT>(a, lam, x, z);
+#pragma unroll
+    for (int l = 0; l < Q; ++l) __builtin_nontemporal_store((L)adj_g<A, L>(c, lam, l), &out[own + (size_t)l * TILE]);
+}
+
+// Rows per block of the gather form: a whole tile with float buffers, half
+// a tile with double ones (measured: 512 x 1536 double 0.110 ms with 256
+// rows vs 0.145 ms with 512; 2048 x 6144 all-float 0.718 ms with 512 vs 0.734).
+template <typename L>
+struct GatherRows {
+    static constexpr int value = sizeof(L) == 4 ? 512 : 256;
+    static_assert(TILE % value == 0, "a gather block's rows must lie in one tile");
+};
+template <typename L, typename MT, bool SHIFT>
+__global__ __launch_bounds__(GatherRows<L>::value) __attribute__((amdgpu_waves_per_eu(AdjWaves<L, MT>::value)))
+void adjoint_gather_kernel(AdjointArgs a, int nzb) {
+    constexpr int BS = GatherRows<L>::value;
+    const int x = (int)(blockIdx.x / (uint32_t)nzb);
+    const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BS;
+    const bool edge = SHIFT ? (z0 < 3) || (z0 + BS + 3 > a.lz) : (z0 + BS > a.lz);
+    if (edge)
+        adjoint_gather_tile<true, SHIFT, L, MT>(a, x, z0);
+    else
+        adjoint_gather_tile<false, SHIFT, L, MT>(a, x, z0);
+}
+
+// Diffuse wall, gather form: A(s) of every ghost site s = (xg, row) into
+// a.wall_a [2 x 3][Lx] from the input mu, before the gather step reads it.
+template <typename L, typename GT>
+__global__ __launch_bounds__(BLOCK) void adjoint_gather_wall(AdjointArgs a) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= 6 * a.lx) return;
+    const L *__restrict__ mu = static_cast<const L *>(a.lam_in);
+    const int xg = t % a.lx, row = t / a.lx;      // row = side * 3 + i
+    const int k = row < 3 ? -1 - row : a.lz + (row - 3);
+    const GT *gh = static_cast<const GT *>(a.ghost) + (size_t)row * Q;
+    constexpr bool dev = std::is_same<GT, float>::value;   // FP32 table stores f - w
+    double S = 0.0, A = 0.0;
+#pragma unroll
+    for (int m = 1; m < Q; ++m) {
+        const int zd = k + EZ[m];   // the ghost site emits population m to (xg + e_mx, zd)
+        if (zd < 0 || zd >= a.lz) continue;
+        const double c = (double)gh[m] + (dev ? W[m] : 0.0);
+        const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
+        S += c;
+        A += c * (double)mu[pidx(m, xd, zd, a.lx)];
+    }
+    a.wall_a[t] = A / S;
+}
+
+template <typename L, typename MT>
+static void launch_gather_t(const AdjointArgs &a, bool shift, hipStream_t s) {
+    constexpr int BS = GatherRows<L>::value;
+    const int nzb = (a.lz + BS - 1) / BS;
+    const dim3 grid((uint32_t)nzb * (uint32_t)a.lx);
+    if (shift)
+        hipLaunchKernelGGL((adjoint_gather_kernel<L, MT, true>), grid, dim3(BS), 0, s, a, nzb);
+    else
+        hipLaunchKernelGGL((adjoint_gather_kernel<L, MT, false>), grid, dim3(BS), 0, s, a, nzb);
+}
+
+hipError_t launch_adjoint_gather(const AdjointArgs &a, bool shift, hipStream_t s) {
+    const bool f32 = (a.flags & F_ADJ_F32) != 0;
+    const bool m32 = (a.flags & F_MOM_F32) != 0;
+    if (shift && (a.flags & F_WALL_DIFFUSE) && !(a.flags & F_PERIODIC_Z)) {
+        const dim3 wgrid((uint32_t)((6 * a.lx + BLOCK - 1) / BLOCK));
+        const bool gf = a.precision == P_F32_DEV;
+        if (f32 && gf)
+            hipLaunchKernelGGL((adjoint_gather_wall<float, float>), wgrid, dim3(BLOCK), 0, s, a);
+        else if (f32)
+            hipLaunchKernelGGL((adjoint_gather_wall<float, double>), wgrid, dim3(BLOCK), 0, s, a);
+        else if (gf)
+            hipLaunchKernelGGL((adjoint_gather_wall<double, float>), wgrid, dim3(BLOCK), 0, s, a);
+        else
+            hipLaunchKernelGGL((adjoint_gather_wall<double, double>), wgrid, dim3(BLOCK), 0, s, a);
+    }
+    if (f32 && m32)
+        launch_gather_t<float, float>(a, shift, s);
+    else if (f32)
+        launch_gather_t<float, double>(a, shift, s);
+    else if (m32)
+        launch_gather_t<double, float>(a, shift, s);
+    else
+        launch_gather_t<double, double>(a, shift, s);
     return hipGetLastError();
 }
 

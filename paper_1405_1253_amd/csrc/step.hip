@@ -147,11 +147,13 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
     const bool periodic = (a.flags & F_PERIODIC_Z) != 0;
 
     // ---- propagate + bc: the incoming population l ------------------------
-    // Interior tiles of the two-buffer step address rows relative to this
-    // block's tile (one tile per block: zt is uniform); every other path
-    // uses the general tiled index.
-    const int zt = two && !EDGE ? __builtin_amdgcn_readfirstlane(z / TILE) : 0;
-    const int zl = z % TILE;
+    // The two-buffer step's tile blocks (one tile per block: zt is uniform)
+    // address rows relative to their tile, also in the tiles at the walls;
+    // the diffuse wall blocks (one wavefront per column, rows of two tiles)
+    // and the in-place kinds use the general tiled index.
+    constexpr bool tile_rows = two && !DIFFUSE;
+    const int zt = tile_rows ? __builtin_amdgcn_readfirstlane(z / TILE) : 0;
+    const int zl = z % TILE, zlq = zq % TILE;
     const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
     auto gather = [&](int l) -> E {
         // in-range value: pulled from the neighbour, or (IN_E) this site's -l slot
@@ -185,10 +187,19 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
 #pragma unroll
         for (int l = 0; l < Q; ++l) {
             const int xs = EX[l] == 0 ? x : wrap(x - EX[l], a.lx);
+            const E *tb = fin + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
             if (!EDGE) {
                 // row z - e_lz: this tile, or (|e_lz| rows) the one below / above
-                const E *tb = fin + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
                 v[l] = tb[tile_off(l, zl - EZ[l], tstep)];
+            } else if (tile_rows && !periodic) {
+                // a tile at a wall: in-range rows as in the interior, ghost rows from the table
+                const int zs = zq - EZ[l];
+                if (zs < 0)
+                    v[l] = ghost[(-zs - 1) * Q + l];
+                else if (zs >= a.lz)
+                    v[l] = ghost[(3 + zs - a.lz) * Q + l];
+                else
+                    v[l] = tb[tile_off(l, zlq - EZ[l], tstep)];
             } else {
                 auto src = [&](int zz) -> E { return fin[pidx(l, xs, zz, a.lx)]; };
                 const int zs = zq - EZ[l];
@@ -224,7 +235,7 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
     // written back (measured 3 % faster on MI355X).
     auto put = [&](int l, E val) {
         if (MODE == M_PULL) {
-            if (!EDGE)
+            if (tile_rows)
                 __builtin_nontemporal_store(
                     val, &fout[((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)l * TILE + zl]);
             else
@@ -488,13 +499,22 @@ __global__ __launch_bounds__(256) void wall_ratio_kernel(StepArgs a) {
                                    row % 3, xg);
 }
 
+// One block (8 wavefronts, 2 per SIMD) per CU at a time.  The kernel needs
+// 126 (FP64) / 80 (FP32) VGPRs, which would let 2 / 3 blocks share a CU;
+// those ran 3.3 % / 4.5 % slower at 4096 x 12288 on MI355X (more tiles in
+// flight at once contend for DRAM banks), so each launch requests this much
+// dynamic LDS, which the kernel never touches, to keep a second block off
+// the CU (160 KB of LDS per CU).
+constexpr size_t STEP_OCCUPANCY_LDS = 80 * 1024;
+
 template <int PREC>
 static void launch_prec(const StepArgs &a, hipStream_t s) {
     constexpr int BS = StepShape<PREC>::BS, span = BS * StepShape<PREC>::ZT;
     const int nzb = (a.lz + span - 1) / span;
     const uint32_t nblocks = (uint32_t)nzb * (uint32_t)a.lx;
     const uint32_t nwall = (a.flags & F_WALL_DIFFUSE) ? (uint32_t)((a.lx + BS / 64 - 1) / (BS / 64)) : 0u;
-    hipLaunchKernelGGL(step_kernel<PREC>, dim3(nwall + nblocks), dim3(BS), 0, s, a, nzb, nblocks, nwall);
+    hipLaunchKernelGGL(step_kernel<PREC>, dim3(nwall + nblocks), dim3(BS), STEP_OCCUPANCY_LDS, s, a, nzb, nblocks,
+                       nwall);
 }
 
 template <int PREC, int MODE>

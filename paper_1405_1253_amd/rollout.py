@@ -2,7 +2,8 @@
 
 J = wk * KE(f*_N) + wl * (L_u + L_d)(f*_N) for f*_N = step^N(init_rt3(amp)),
 with the mixing lengths of Sec. IV (eq. 3L).  The backward pass runs the
-library's adjoint kernels (lbm_objective seed, lbm_adjoint_step,
+library's adjoint kernels (lbm_objective seed; lbm_adjoint_collide, then
+lbm_adjoint_gather per step, or lbm_adjoint_step per step in push form;
 lbm_init_rt3_vjp); this module only schedules them and manages memory.
 
 Memory schedule (two levels):
@@ -52,6 +53,11 @@ class RolloutConfig:
     adj_precision: str = "f64"     # "f32": adjoint buffers in float (LBM_ADJ_F32)
     wall: str = "dirichlet"        # or "diffuse" (LBM_WALL_DIFFUSE)
     mom_precision: str = "f64"     # "f32": stored moments in float (LBM_MOM_F32)
+    # "gather" (lbm_adjoint_collide, lbm_adjoint_gather), "push" (lbm_adjoint_step)
+    # or "auto": gather with float adjoint buffers, push with double ones (the
+    # faster form of each on MI355X: 2048 x 6144 all-float 0.72 ms gather vs
+    # 0.82 ms push; 512 x 1536 double 0.110 ms vs 0.104 ms)
+    adjoint_form: str = "auto"
 
     @classmethod
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
@@ -125,6 +131,14 @@ class Rollout:
             self.segbuf = self.kept[:self.ckpt_every]       # reused once the sweep has passed it
         else:
             self.segbuf = torch.empty((self.ckpt_every, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
+        if c.adjoint_form not in ("gather", "push", "auto"):
+            raise ValueError(f"unknown adjoint form {c.adjoint_form!r}")
+        if c.adjoint_form == "auto":
+            self.form = "gather" if c.adj_precision == "f32" else "push"
+        else:
+            self.form = c.adjoint_form
+        p = self.params
+        self.params_stream = abi.make_params(c.lx, c.lz, c.tau, c.g, p.precision, p.flags | abi.NO_COLLIDE)
         self.ckpt = {}
         self.recomputed_steps = 0
 
@@ -177,7 +191,21 @@ class Rollout:
                 continue
             _, t, where, i = op
             mom = self.kept[i] if where == "kept" else self.segbuf[i]
-            abi.lbm_adjoint_step(self.params, self.ghost, mom, self.lam[li], self.lam[1 - li])
+            src, dst = self.lam[li], self.lam[1 - li]
+            if self.form == "push":
+                # lam_{t-1} = S^T C_t^T lam_t
+                abi.lbm_adjoint_step(self.params, self.ghost, mom, src, dst)
+            elif t == c.nsteps:
+                # mu_N = C_N^T lam_N
+                abi.lbm_adjoint_collide(self.params, mom, src, dst)
+            else:
+                # mu_t = C_t^T S^T mu_{t+1}
+                abi.lbm_adjoint_gather(self.params, self.ghost, mom, src, dst, self.scratch)
+            li = 1 - li
+        if self.form == "gather" and c.nsteps > 0:
+            # lam_0 = S^T mu_1
+            abi.lbm_adjoint_gather(self.params_stream, self.ghost, None, self.lam[li], self.lam[1 - li],
+                                   self.scratch)
             li = 1 - li
         d_amp = torch.empty_like(self.amp)
         abi.lbm_init_rt3_vjp(self.params, self.desc, self.amp, self.lam[li], d_amp, self.scratch)
