@@ -37,20 +37,29 @@ def bytes_per_site(precision):
     return 2 * Q * (8 if precision == "f64" else 4)      # 37 reads + 37 writes
 
 
-def step_source_hash():
+def code_hash(names):
+    """sha256 (16 hex digits) of the named kernel sources with comments and
+    blank lines removed: a counter summary stays valid across comment edits
+    and is invalidated by any change to the code."""
     h = hashlib.sha256()
-    for name in ("step.hip", "common.h", "lattice_constants.h"):
-        with open(os.path.join(ROOT, "paper_1405_1253_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1405_1253_amd", "csrc", name)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        for line in text.splitlines():
+            line = line.strip()
+            if line:
+                h.update(line.encode() + b"\n")
     return h.hexdigest()[:16]
+
+
+def step_source_hash():
+    return code_hash(("step.hip", "common.h", "lattice_constants.h"))
 
 
 def adjoint_source_hash():
-    h = hashlib.sha256()
-    for name in ("adjoint.hip", "common.h", "lattice_constants.h"):
-        with open(os.path.join(ROOT, "paper_1405_1253_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return code_hash(("adjoint.hip", "common.h", "lattice_constants.h"))
 
 
 def measured_adjoint_traffic(workload):

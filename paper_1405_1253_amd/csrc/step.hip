@@ -376,11 +376,10 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
 }
 
 // Launch shape per precision: threads per block (one site each along z) and
-// the number of consecutive tiles of BS rows each block walks.  Walking
-// several tiles of one column lets the cache lines that neighbouring tiles
-// share (pull sources shifted by up to 3 rows) be re-read from this block's
-// L2 instead of being fetched again by a block on another XCD.  Chosen by
-// measurement on MI355X at 4096 x 12288 (FP64 512 x 2, FP32 256 x 2).
+// the number of consecutive row blocks of BS rows each block walks.  A block
+// covers exactly one 512-row tile of the population layout in both
+// precisions: the interior path addresses rows relative to the tile's base
+// (common.h tile_off), with the tile index uniform over the block.
 template <int PREC>
 struct StepShape;
 template <>
@@ -504,7 +503,8 @@ __global__ __launch_bounds__(256) void wall_ratio_kernel(StepArgs a) {
 // those ran 3.3 % / 4.5 % slower at 4096 x 12288 on MI355X (more tiles in
 // flight at once contend for DRAM banks), so each launch requests this much
 // dynamic LDS, which the kernel never touches, to keep a second block off
-// the CU (160 KB of LDS per CU).
+// the CU: with the kernel's static array of wall ratios (2.6 KB) a block
+// takes more than half of the CU's 160 KB.
 constexpr size_t STEP_OCCUPANCY_LDS = 80 * 1024;
 
 template <int PREC>
