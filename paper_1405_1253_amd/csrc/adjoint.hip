@@ -163,16 +163,32 @@ struct AdjSite {
     A gk, ga, gbx, gbz, gg;
 };
 
-template <typename A, typename L, typename MT>
-__device__ __forceinline__ AdjSite<A> adj_site(const AdjointArgs &a, const L lam[Q], int x, int z) {
-    double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
+// The stored pre-collision moments of site (x, z) (none with F_NO_COLLIDE,
+// where a.mom may be null).
+struct SiteMoments {
+    double rho, ux, uz, T;
+};
+template <typename MT>
+__device__ __forceinline__ SiteMoments load_moments(const AdjointArgs &a, int x, int z) {
+    SiteMoments m{1.0, 0.0, 0.0, 1.0};
     if (!(a.flags & F_NO_COLLIDE)) {
         // moments [4][Lx][Lz]: uniform column base + 32-bit per-lane byte offset
         const size_t N = (size_t)a.lx * (size_t)a.lz;
         const MT *mcol = static_cast<const MT *>(a.mom) + (size_t)x * (size_t)a.lz;
         const uint32_t moff = (uint32_t)z * (uint32_t)sizeof(MT);
-        const double rho = ldg_off(mcol, moff), ux = ldg_off(mcol + N, moff),
-                     uz = ldg_off(mcol + 2 * N, moff), T = ldg_off(mcol + 3 * N, moff);
+        m.rho = ldg_off(mcol, moff);
+        m.ux = ldg_off(mcol + N, moff);
+        m.uz = ldg_off(mcol + 2 * N, moff);
+        m.T = ldg_off(mcol + 3 * N, moff);
+    }
+    return m;
+}
+
+template <typename A, typename L>
+__device__ __forceinline__ AdjSite<A> adj_site(const AdjointArgs &a, const L lam[Q], const SiteMoments &m) {
+    double keep = 1.0, alpha = 0.0, bx = 0.0, bz = 0.0, gamma = 0.0;
+    if (!(a.flags & F_NO_COLLIDE)) {
+        const double rho = m.rho, ux = m.ux, uz = m.uz, T = m.T;
         const double vx = ux, vz = uz - a.tau * a.g;
         const double th = T + a.tau * (1.0 - a.tau) * a.g * a.g / D - 1.0;
         const EqVjp s = eq_vjp_sums<A>(lam, vx, vz, th);
@@ -222,7 +238,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjointArgs &a, int x, int z0
     L lam[Q];   // held in the buffer's type (float buffers: half the registers)
 #pragma unroll
     for (int l = 0; l < Q; ++l) lam[l] = lam_in[own + (size_t)l * TILE];
-    const AdjSite<A> c = adj_site<A, L, MT>(a, lam, x, z);
+    const AdjSite<A> c = adj_site<A, L>(a, lam, load_moments<MT>(a, x, z));
     auto gval = [&](int l) -> A { return adj_g<A, L>(c, lam, l); };
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
@@ -387,6 +403,9 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
     const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
     const size_t own = ((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)zl;   // (0, x, z)
     const bool periodic = (a.flags & F_PERIODIC_Z) != 0, diffuse = (a.flags & F_WALL_DIFFUSE) != 0;
+    // the moments first: their loads overlap the 37 gathers (measured 2 %
+    // faster than after them, with 4 wavefronts per SIMD)
+    const SiteMoments m = load_moments<MT>(a, x, z);
     L lam[Q];
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
@@ -415,23 +434,28 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
             lam[l] = L(0);
         }
     }
-    const AdjSite<A> c = adj_site<A, L, MT>(a, lam, x, z);
+    const AdjSite<A> c = adj_site<A, L>(a, lam, m);
 #pragma unroll
     for (int l = 0; l < Q; ++l) __builtin_nontemporal_store((L)adj_g<A, L>(c, lam, l), &out[own + (size_t)l * TILE]);
 }
 
-// Rows per block of the gather form: a whole tile with float buffers, half
-// a tile with double ones (measured: 512 x 1536 double 0.110 ms with 256
-// rows vs 0.145 ms with 512; 2048 x 6144 all-float 0.718 ms with 512 vs 0.734).
-template <typename L>
-struct GatherRows {
-    static constexpr int value = sizeof(L) == 4 ? 512 : 256;
-    static_assert(TILE % value == 0, "a gather block's rows must lie in one tile");
+// Launch shape of the gather form: 256 rows per block (a tile holds two
+// such blocks); 4 wavefronts per SIMD with float buffers and float moments
+// (128 VGPRs, no spills), 2 otherwise.  Measured on MI355X, 2048 x 6144
+// all-float: 0.704 ms, against 0.718 with 512-row blocks at 3 wavefronts
+// per SIMD, 0.726 with 256 rows and the moments loaded after the gathers,
+// 0.737 with non-temporal gathers and 0.724 with XCD-contiguous tile order;
+// 512 x 1536 double: 0.110 ms with 256 rows vs 0.145 with 512.
+constexpr int GATHER_BS = 256;
+static_assert(TILE % GATHER_BS == 0, "a gather block's rows must lie in one tile");
+template <typename L, typename MT>
+struct GatherWaves {
+    static constexpr int value = (sizeof(L) == 4 && sizeof(MT) == 4) ? 4 : 2;
 };
 template <typename L, typename MT, bool SHIFT>
-__global__ __launch_bounds__(GatherRows<L>::value) __attribute__((amdgpu_waves_per_eu(AdjWaves<L, MT>::value)))
+__global__ __launch_bounds__(GATHER_BS) __attribute__((amdgpu_waves_per_eu(GatherWaves<L, MT>::value)))
 void adjoint_gather_kernel(AdjointArgs a, int nzb) {
-    constexpr int BS = GatherRows<L>::value;
+    constexpr int BS = GATHER_BS;
     const int x = (int)(blockIdx.x / (uint32_t)nzb);
     const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BS;
     const bool edge = SHIFT ? (z0 < 3) || (z0 + BS + 3 > a.lz) : (z0 + BS > a.lz);
@@ -467,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_gather_wall(AdjointArgs a) {
 
 template <typename L, typename MT>
 static void launch_gather_t(const AdjointArgs &a, bool shift, hipStream_t s) {
-    constexpr int BS = GatherRows<L>::value;
+    constexpr int BS = GATHER_BS;
     const int nzb = (a.lz + BS - 1) / BS;
     const dim3 grid((uint32_t)nzb * (uint32_t)a.lx);
     if (shift)

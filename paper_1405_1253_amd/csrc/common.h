@@ -25,12 +25,6 @@ namespace lbm {
 #ifndef LBM_BLOCK
 #define LBM_BLOCK 256
 #endif
-// XCD-contiguous tile order (see xcd_tile).  Off by default: on the
-// 37 + 37-stream pull pattern it measured 4-7 % slower than the hardware's
-// round-robin order on MI355X.
-#ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 0
-#endif
 constexpr int BLOCK = LBM_BLOCK;   // threads per block, one site each along z
 constexpr double D = 2.0;    // space dimension
 
@@ -126,16 +120,6 @@ __device__ __forceinline__ long long tile_off(int l, int rl, long long step) {
 __device__ __forceinline__ int wrap(int i, int n) {
     int m = i % n;
     return m < 0 ? m + n : m;
-}
-
-// Map the hardware block index onto a logical tile index so that each XCD
-// (blocks are dealt round-robin over 8 XCDs) gets a contiguous range of
-// tiles: neighbouring tiles then share that XCD's L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks) {
-    if (!LBM_XCD_REMAP) return b;
-    const uint32_t nx = 8, q = nblocks / nx, rem = nblocks % nx;
-    const uint32_t j = b % nx, i = b / nx;
-    return (j < rem ? j * (q + 1) : rem * (q + 1) + (j - rem) * q) + i;
 }
 
 }  // namespace lbm

@@ -41,7 +41,8 @@ def test_traffic_only_for_the_profiled_source(monkeypatch):
 
 @pytest.mark.parametrize("name", ["step.hip", "common.h", "lattice_constants.h"])
 def test_source_hash_covers_the_step_sources(name, monkeypatch, tmp_path):
-    """Changing any file the step kernel is built from changes the hash."""
+    """Changing the code of any file the step kernel is built from changes
+    the hash; a comment or a blank line does not."""
     csrc = tmp_path / "paper_1405_1253_amd" / "csrc"
     csrc.mkdir(parents=True)
     for n in ("step.hip", "common.h", "lattice_constants.h"):
@@ -49,8 +50,11 @@ def test_source_hash_covers_the_step_sources(name, monkeypatch, tmp_path):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h0 = bench.step_source_hash()
     assert h0 == bench.step_source_hash()
-    with open(csrc / name, "ab") as fh:
-        fh.write(b"\n")
+    with open(csrc / name, "a") as fh:
+        fh.write("\n// a comment\n/* another\n   comment */\n\n")
+    assert bench.step_source_hash() == h0
+    with open(csrc / name, "a") as fh:
+        fh.write("static int extra_symbol;\n")
     assert bench.step_source_hash() != h0
 
 

@@ -5,8 +5,8 @@ transpose S^T (pull_transpose: a gather y <- y + e_l, zero or the diffuse
 wall's ghost-site sum beyond the walls).  Bars as for lbm_adjoint_step:
 1e-12 of the largest entry in double; the float bounds of test_gpu_adjoint
 otherwise.  A rollout in gather form gives the push form's gradient to
-rounding.  Shapes include interior 512-row tiles
-and ragged tails."""
+rounding.  Shapes include interior 256-row blocks (Lz >= 515) and ragged
+tails."""
 import numpy as np
 import pytest
 import torch

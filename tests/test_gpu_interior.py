@@ -2,11 +2,11 @@
 
 The step kernel gives a tile the branch-free (interior) code only when none
 of its rows pulls from within 3 rows of a wall or of the lattice end: tile
-rows [z0, z0 + BS) with z0 >= 3 and z0 + BS + 3 <= Lz, BS = 512 rows in FP64
-and 256 in FP32.  The adjoint step's tiles are 256 rows.  So interior tiles
-need Lz >= 1027 (FP64 step) and Lz >= 515 (FP32 step, adjoint step); every
-large lattice spends almost all of its time in them.  These tests take
-shapes with several interior tiles and a ragged tail:
+rows [z0, z0 + BS) with z0 >= 3 and z0 + BS + 3 <= Lz, BS = 512 rows in both
+precisions.  The adjoint kernels' blocks are 256 rows (push form and gather
+form).  So interior tiles need Lz >= 1027 (step) and Lz >= 515 (adjoint);
+every large lattice spends almost all of its time in them.  These tests
+take shapes with several interior tiles and a ragged tail:
 
 * streaming (LBM_NO_COLLIDE), walled and periodic, both precisions: bit-exact
   (a pure permutation, Sec. III.B propagate);

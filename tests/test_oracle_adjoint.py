@@ -35,6 +35,39 @@ def test_step_vjp_dot_product(periodic):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+def test_collide_vjp_dot_product():
+    """C^T alone: <lam, (d collide/dg) v> = <collide_vjp(lam, g), v>, the
+    Jacobian-vector product by complex step of the forward collide."""
+    lx, lz = 5, 6
+    p = O.Params(lx, lz, 0.65, 2e-3)
+    g = _near_eq(4, lx, lz)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(g.shape)
+    lam = rng.standard_normal(g.shape)
+    jv = np.imag(O.collide(g + 1j * H * v, p)) / H
+    lhs = np.sum(lam * jv)
+    rhs = np.sum(A.collide_vjp(lam, g, p) * v)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("wall,periodic", [("dirichlet", False), ("dirichlet", True), ("diffuse", False)])
+def test_pull_transpose_dot_product(wall, periodic):
+    """S^T alone: <G, (d pull/df) v> = <pull_transpose(G), v> for both wall
+    rules and the periodic test mode (the pull is affine in f: the table
+    rows are constant, the diffuse wall's emissions linear in f)."""
+    lx, lz = 7, 9
+    p = O.Params(lx, lz, 0.65, 2e-3, periodic_z=periodic, wall=wall)
+    f = _near_eq(6, lx, lz)
+    ghost = W.random_ghost(7) * 0.01 + (0.0 if wall == "dirichlet" else 0.02)
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(f.shape)
+    G = rng.standard_normal(f.shape)
+    jv = np.imag(O.pull(f + 1j * H * v, ghost, p)) / H
+    lhs = np.sum(G * jv)
+    rhs = np.sum(A.pull_transpose(G, p, ghost) * v)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
 def test_objective_vjp_matches_complex_step():
     wl = W.WORKLOADS["rt3_128x384"]
     lx, lz = 12, 60
