@@ -9,11 +9,15 @@ populations already resident in HBM.  The default workload is the FP64
 three-layer Rayleigh-Taylor lattice of one GPU's production share,
 4096 x 12288 sites.  Prints one JSON line with MLUPS, the HBM roofline of the
 step kernel (algorithmic bytes / kernel time, timed with HIP events on the
-stream the kernel runs on) and the CPU oracle timed on a bounded sample.
-Secondary figures: the same lattice in FP32 deviation storage, with the
+stream the kernel runs on, plus the HBM bytes of the committed counter
+summary while it matches the kernel code) and the CPU oracle timed on the
+host cores (one process per core, each on its own strip of the lattice).
+Also: the fused step against streaming alone on the same buffers, in
+interleaved windows; the same lattice in FP32 deviation storage, with the
 diffuse (mass-conserving) walls and on a single buffer, both precisions;
 streaming alone in pull and in push form; the adjoint rollouts' cost
-relative to a plain forward.
+relative to a plain forward and the adjoint step's bandwidth (gather form
+with float adjoint buffers, push form with double ones).
 """
 import argparse
 import hashlib
