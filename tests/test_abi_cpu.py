@@ -108,6 +108,37 @@ def test_empty_lattice_is_a_no_op(abi):
         assert abi.lbm_scratch_bytes(abi.make_params(lx, lz, 0.7, 0.0)) == 0
 
 
+def test_every_entry_point_accepts_an_empty_lattice(abi):
+    """Lx = 0 or Lz = 0 is a valid lattice with nothing to do: every entry
+    point that takes params returns LBM_OK without touching the (here
+    fictitious, never dereferenced) device buffers or the HIP runtime, and
+    lbm_population_elems / lbm_scratch_bytes return 0."""
+    lib = abi.load()
+    desc = abi.RT3Desc(1.05, 1.0, 0.95, 4.0, np.ones((2, 2), np.int32), np.zeros((2, 2)))
+    a, b, c, d, e = (1 << 30), (3 << 30), (5 << 30), (7 << 30), (9 << 30)
+    for lx, lz in ((0, 16), (16, 0), (0, 0)):
+        for flags in (0, abi.WALL_DIFFUSE, abi.ADJ_F32 | abi.MOM_F32):
+            p = abi.make_params(lx, lz, 0.7, 1e-4, flags=flags)
+            r = ctypes.byref(p)
+            assert lib.lbm_population_elems(r) == 0 and lib.lbm_scratch_bytes(r) == 0
+            calls = {
+                "init_rt3": lib.lbm_init_rt3(r, ctypes.byref(desc.c), a, b, c, None),
+                "step": lib.lbm_step(r, a, b, c, None, None),
+                "step_inplace": lib.lbm_step_inplace(r, a, b, 0, None, None, 0, None),
+                "pack": lib.lbm_pack(r, a, b, 8, None),
+                "unpack": lib.lbm_unpack(r, a, b, 4, None),
+                "moments": lib.lbm_moments(r, a, b, None, None, None, 0, None),
+                "moments_noalloc": lib.lbm_moments_noalloc(r, a, b, None, None, None),
+                "profiles": lib.lbm_profiles(r, a, b, c, 0, None),
+                "objective": lib.lbm_objective(r, ctypes.byref(desc.c), a, 1.0, 1.0, b, None, c, 0, None),
+                "adjoint_step": lib.lbm_adjoint_step(r, a, b, c, d, None),
+                "adjoint_collide": lib.lbm_adjoint_collide(r, b, c, d, None),
+                "adjoint_gather": lib.lbm_adjoint_gather(r, a, b, c, d, e, 0, None),
+                "init_rt3_vjp": lib.lbm_init_rt3_vjp(r, ctypes.byref(desc.c), a, b, c, d, 0, None),
+            }
+            assert all(v == 0 for v in calls.values()), (lx, lz, flags, calls)
+
+
 def test_moments_and_init_reject_bad_arguments(abi):
     lib = abi.load()
     p = abi.make_params(64, 64, 0.7, 1e-4)
