@@ -3,12 +3,14 @@
 Argument marshalling only -- every step of the method runs in the library's
 HIP kernels.  Population buffers (the state, adjoint buffers) are in the
 library's tiled layout (include/lbm.h); to_tiled / to_soa convert to and from
-the plain [37, Lx, Lz] layout through the library's pack/unpack kernels.  Before a call, each tensor's element type and size are checked
-against what the parameters imply (the C entry points see only addresses),
-so a mismatched buffer raises ValueError instead of being overrun.  Buffers are torch tensors (device memory) or raw integer
-addresses; streams default to torch's current stream.  A failing call raises
-LbmError with the library's status text.  Loading fails loudly when the
-library has not been built: there is no fallback.
+the plain [37, Lx, Lz] layout through the library's pack/unpack kernels.
+Before a call, each tensor's element type and size are checked against what
+the parameters imply (the C entry points see only addresses), so a
+mismatched buffer raises ValueError instead of being overrun.  Buffers are
+torch tensors (device memory) or raw integer addresses (passed unchecked);
+streams default to torch's current stream.  A failing call raises LbmError
+with the library's status text.  Loading fails loudly when the library has
+not been built: there is no fallback.
 """
 import ctypes
 import os
@@ -125,7 +127,7 @@ def _ptr(x):
     if not x.is_cuda:
         raise ValueError("liblbm buffers must be GPU tensors")
     if not x.is_contiguous():
-        raise ValueError("liblbm buffers must be contiguous (layout [37][Lx][Lz], z fastest)")
+        raise ValueError("liblbm buffers must be contiguous (the layouts of include/lbm.h)")
     return x.data_ptr()
 
 

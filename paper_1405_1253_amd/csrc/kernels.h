@@ -64,8 +64,8 @@ hipError_t launch_init(const InitArgs &a, int precision, hipStream_t s);
 
 struct AdjointArgs {
     const void *mom;       // [4][lx][lz] pre-collision moments of the step (double, or float with F_MOM_F32)
-    const void *lam_in;    // [37][lx][lz] dJ/df*_t (double, or float with F_ADJ_F32)
-    void *lam_out;         // [37][lx][lz] dJ/df*_{t-1}
+    const void *lam_in;    // population buffer (tiled) dJ/df*_t (double, or float with F_ADJ_F32)
+    void *lam_out;         // population buffer (tiled) dJ/df*_{t-1}
     const void *ghost;     // [2][3][37] wall table of the forward step (F_WALL_DIFFUSE)
     int precision;         // element type of ghost (P_F64 / P_F32_DEV)
     int lx, lz;
@@ -82,7 +82,7 @@ struct ObjectiveArgs {
     const void *f;
     void *scratch;
     double *j_out;         // [5]: J, KE, L_u + L_d, L_u, L_d
-    void *lam_seed;        // nullable [37][lx][lz], double or float
+    void *lam_seed;        // nullable population buffer (tiled), double or float
     int lx, lz;
     bool lam_f32;
     double g, t_d, t_m, t_u, wk, wl;
@@ -91,7 +91,7 @@ size_t objective_scratch_bytes(int lx, int lz);
 hipError_t launch_objective(const ObjectiveArgs &a, int precision, hipStream_t s);
 
 struct InitVjpArgs {
-    const void *lam0;      // [37][lx][lz], double or float
+    const void *lam0;      // population buffer (tiled), double or float
     bool lam_f32;
     const double *amp;     // [2][nmodes]
     double *d_amp;         // [2][nmodes]

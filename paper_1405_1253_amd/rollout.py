@@ -55,8 +55,8 @@ class RolloutConfig:
     mom_precision: str = "f64"     # "f32": stored moments in float (LBM_MOM_F32)
     # "gather" (lbm_adjoint_collide, lbm_adjoint_gather), "push" (lbm_adjoint_step)
     # or "auto": gather with float adjoint buffers, push with double ones (the
-    # faster form of each on MI355X: 2048 x 6144 all-float 0.72 ms gather vs
-    # 0.82 ms push; 512 x 1536 double 0.110 ms vs 0.104 ms)
+    # faster form of each on MI355X: 2048 x 6144 all-float 0.70-0.71 ms gather
+    # vs 0.82 ms push; 512 x 1536 double 0.110 ms vs 0.103 ms)
     adjoint_form: str = "auto"
 
     @classmethod
