@@ -326,13 +326,16 @@ __global__ __launch_bounds__(BLOCK) void adjoint_wall_kernel(AdjointArgs a) {
     double S = 0.0, A = 0.0;
 #pragma unroll
     for (int m = 1; m < Q; ++m) {
-        const int zd = k + EZ[m];   // the ghost site emits population m to (xg + e_mx, zd)
-        if (zd < 0 || zd >= a.lz) continue;
+        // the ghost site emits population m to (xg + e_mx, zd); loads from a
+        // clamped row, masked, so that they are all in flight at once
+        const int zd = k + EZ[m];
+        const bool in = zd >= 0 && zd < a.lz;
         const double c = (double)gh[m] + (dev ? W[m] : 0.0);
         const int o = (m & 1) ? m + 1 : m - 1;
         const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
-        S += c;
-        A += c * (double)lam[pidx(o, xd, zd, a.lx)];
+        const double v = (double)lam[pidx(o, xd, zd < 0 ? 0 : (zd >= a.lz ? a.lz - 1 : zd), a.lx)];
+        S += in ? c : 0.0;
+        A += in ? c * v : 0.0;
     }
     const L out = (L)(A / S);
 #pragma unroll
@@ -392,7 +395,10 @@ hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
 // Dirichlet wall and, for the diffuse wall, the ghost site s = y + e_l's sum
 // A(s) = sum_m c_m mu_m(s + e_m) / sum_m c_m over the m pointing back into
 // the lattice (c_m = its table row), formed beforehand by adjoint_gather_wall.
-template <bool EDGE, bool SHIFT, typename L, typename MT>
+// WALL (tiles at a wall or the lattice end only): 0 Dirichlet walls, 1
+// diffuse walls, 2 periodic in z, fixed at compile time so that the gather's
+// loads sit in no branch.
+template <bool EDGE, bool SHIFT, typename L, typename MT, int WALL = 0>
 __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x, int z0) {
     using A = AdjAcc<L, MT>;
     const L *__restrict__ in = static_cast<const L *>(a.lam_in);
@@ -402,7 +408,6 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
     const int zt = z0 / TILE, zl = z % TILE;
     const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
     const size_t own = ((size_t)zt * (size_t)a.lx + (size_t)x) * (Q * TILE) + (size_t)zl;   // (0, x, z)
-    const bool periodic = (a.flags & F_PERIODIC_Z) != 0, diffuse = (a.flags & F_WALL_DIFFUSE) != 0;
     // the moments first: their loads overlap the 37 gathers (measured 2 %
     // faster than after them, with 4 wavefronts per SIMD)
     const SiteMoments m = load_moments<MT>(a, x, z);
@@ -421,18 +426,23 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
             continue;
         }
         const int zs = z + EZ[l];
-        if (periodic) {
+        if (WALL == 2) {
             lam[l] = in[pidx(l, xs, wrap(zs, a.lz), a.lx)];
-        } else if (zs >= 0 && zs < a.lz) {
-            // in-range rows as in the interior
-            const L *tb = in + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
-            lam[l] = tb[tile_off(l, zl + EZ[l], tstep)];
-        } else if (diffuse) {   // ghost site (x + e_lx, zs)
-            const int row = zs < 0 ? -zs - 1 : 3 + zs - a.lz;
-            lam[l] = (L)a.wall_a[(size_t)row * (size_t)a.lx + (size_t)xs];
-        } else {
-            lam[l] = L(0);
+            continue;
         }
+        // Loads without per-lane branches (loads under such branches are
+        // issued one at a time): the in-range candidate from a clamped row
+        // (within 3 rows of z, so tile_off still applies), the diffuse ghost
+        // site's sum for a clamped ghost row, then a select.
+        const int zc = zs < 0 ? 0 : (zs >= a.lz ? a.lz - 1 : zs);
+        const L *tb = in + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
+        const L inval = tb[tile_off(l, zl + (zc - z), tstep)];
+        L ghostval = L(0);
+        if (WALL == 1) {   // ghost site (x + e_lx, zs)
+            const int row = zs < 0 ? -zs - 1 : (zs >= a.lz ? 3 + zs - a.lz : 0);
+            ghostval = (L)a.wall_a[(size_t)row * (size_t)a.lx + (size_t)xs];
+        }
+        lam[l] = (zs >= 0 && zs < a.lz) ? inval : ghostval;
     }
     const AdjSite<A> c = adj_site<A, L>(a, lam, m);
 #pragma unroll
@@ -445,7 +455,9 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
 // all-float: 0.704 ms, against 0.718 with 512-row blocks at 3 wavefronts
 // per SIMD, 0.726 with 256 rows and the moments loaded after the gathers,
 // 0.737 with non-temporal gathers and 0.724 with XCD-contiguous tile order;
-// 512 x 1536 double: 0.110 ms with 256 rows vs 0.145 with 512.
+// 512 x 1536 double: 0.110 ms with 256 rows vs 0.145 with 512.  With the
+// wall tiles' loads free of per-lane branches (above): 0.693 ms and
+// 0.082 ms.
 constexpr int GATHER_BS = 256;
 static_assert(TILE % GATHER_BS == 0, "a gather block's rows must lie in one tile");
 template <typename L, typename MT>
@@ -459,10 +471,16 @@ void adjoint_gather_kernel(AdjointArgs a, int nzb) {
     const int x = (int)(blockIdx.x / (uint32_t)nzb);
     const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BS;
     const bool edge = SHIFT ? (z0 < 3) || (z0 + BS + 3 > a.lz) : (z0 + BS > a.lz);
-    if (edge)
-        adjoint_gather_tile<true, SHIFT, L, MT>(a, x, z0);
-    else
+    if (!edge)
         adjoint_gather_tile<false, SHIFT, L, MT>(a, x, z0);
+    else if (!SHIFT)
+        adjoint_gather_tile<true, false, L, MT>(a, x, z0);
+    else if (a.flags & F_PERIODIC_Z)
+        adjoint_gather_tile<true, true, L, MT, 2>(a, x, z0);
+    else if (a.flags & F_WALL_DIFFUSE)
+        adjoint_gather_tile<true, true, L, MT, 1>(a, x, z0);
+    else
+        adjoint_gather_tile<true, true, L, MT, 0>(a, x, z0);
 }
 
 // Diffuse wall, gather form: A(s) of every ghost site s = (xg, row) into
@@ -479,12 +497,15 @@ __global__ __launch_bounds__(BLOCK) void adjoint_gather_wall(AdjointArgs a) {
     double S = 0.0, A = 0.0;
 #pragma unroll
     for (int m = 1; m < Q; ++m) {
-        const int zd = k + EZ[m];   // the ghost site emits population m to (xg + e_mx, zd)
-        if (zd < 0 || zd >= a.lz) continue;
+        // the ghost site emits population m to (xg + e_mx, zd); loads from a
+        // clamped row, masked, so that they are all in flight at once
+        const int zd = k + EZ[m];
+        const bool in = zd >= 0 && zd < a.lz;
         const double c = (double)gh[m] + (dev ? W[m] : 0.0);
         const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
-        S += c;
-        A += c * (double)mu[pidx(m, xd, zd, a.lx)];
+        const double v = (double)mu[pidx(m, xd, zd < 0 ? 0 : (zd >= a.lz ? a.lz - 1 : zd), a.lx)];
+        S += in ? c : 0.0;
+        A += in ? c * v : 0.0;
     }
     a.wall_a[t] = A / S;
 }

@@ -106,35 +106,68 @@ __device__ __forceinline__ double ghost_ratio(const StepArgs &a, const E *f, con
     double M = 0.0, S = 0.0;
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
+        // every load unconditional (a clamped row where the source lies beyond
+        // the wall), then masked: loads under per-lane branches are issued one
+        // at a time, each waiting for the previous
         const int zs = k - EZ[m];
-        if (zs >= 0 && zs < a.lz) {
-            const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
-            M += full_value<PREC>(f[pidx(m, xs, zs, a.lx)], m);
-        }
+        const int zc = zs < 0 ? 0 : (zs >= a.lz ? a.lz - 1 : zs);
+        const int xs = EX[m] == 0 ? xg : wrap(xg - EX[m], a.lx);
+        const double v = full_value<PREC>(f[pidx(m, xs, zc, a.lx)], m);
+        M += (zs >= 0 && zs < a.lz) ? v : 0.0;
         const int zd = k + EZ[m];
-        if (zd >= 0 && zd < a.lz) S += full_value<PREC>(row[m], m);
+        const double c = full_value<PREC>(row[m], m);
+        S += (zd >= 0 && zd < a.lz) ? c : 0.0;
     }
     return M / S;
 }
 
-// M/S for the 2 x 3 x 7 ghost sites (side, row i, column x + dx), dx = -3..3,
-// that column x pulls from, one lane each (lanes 0..41 of a wavefront).
+// Diffuse wall: the incoming population l at a site whose pull source row zs
+// may lie beyond a wall.  `in` is the in-range candidate, already loaded from
+// a valid row; gv[side][i][l] (LDS) holds what ghost site (x - e_lx, row i of
+// the side) emits into population l, and the two are selected without a
+// branch: a global load under a per-lane branch is waited for on its own.
 template <int PREC, typename E>
-__device__ __forceinline__ void diffuse_wall_ratios(const StepArgs &a, const E *fin, const E *ghost, int x,
-                                                    int lane, double (*ratio)[3][7]) {
-    if (lane >= 42) return;
-    const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
-    ratio[side][i][dx + 3] = ghost_ratio<PREC>(a, fin, ghost, side, i, wrap(x + dx, a.lx));
+__device__ __forceinline__ E diffuse_source(E in, const double (*gv)[3][Q], int l, int zs, int lz) {
+    const bool gs = zs < 0 || zs >= lz;
+    const int side = zs < 0 ? 0 : 1;
+    const int i = zs < 0 ? -zs - 1 : (zs >= lz ? zs - lz : 0);
+    const double f = gv[side][i][l];
+    return gs ? (E)(PREC == P_F64 ? f : f - W[l]) : in;
+}
+
+// The diffuse wall's ghost values of one column x, by one wavefront: lanes
+// 0..41 form M/S of the 2 x 3 x 7 ghost sites (side, row i, column x + dx),
+// dx = -3..3, that the column pulls from (into ratio), then every lane forms
+// gv[side][i][l] = table[side][i][l] M/S of the ghost site in column x - e_lx.
+// `ratio_in`, if given, holds M/S of every ghost site ([2 x 3][Lx], formed
+// beforehand) instead.  The caller synchronises the block between the two
+// phases (`phase` 0 and 1).
+template <int PREC, typename E>
+__device__ __forceinline__ void diffuse_ghost_values(const StepArgs &a, const E *fin, const E *ghost,
+                                                     const double *ratio_in, int x, int lane, int phase,
+                                                     double (*ratio)[3][7], double (*gv)[3][Q]) {
+    if (phase == 0) {
+        if (lane >= 42) return;
+        const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
+        const int xg = wrap(x + dx, a.lx);
+        ratio[side][i][dx + 3] = ratio_in ? ratio_in[(size_t)(side * 3 + i) * a.lx + xg]
+                                          : ghost_ratio<PREC>(a, fin, ghost, side, i, xg);
+        return;
+    }
+    for (int j = lane; j < 2 * 3 * Q; j += 64) {
+        const int row = j / Q, l = j % Q;   // row = side * 3 + i
+        gv[row / 3][row % 3][l] = full_value<PREC>(ghost[row * Q + l], l) * ratio[row / 3][row % 3][3 - EX[l]];
+    }
 }
 
 // One site (x, z) of the step.  EDGE: rows within 3 of a wall may pull from
 // ghost sites; lanes with z >= Lz only read (a valid row) and store nothing,
 // nor do lanes with store == false.  DIFFUSE: ghost sites are the diffuse
-// wall's, with M/S from ratio (columns x-3..x+3).  MODE: addressing (see the
-// file comment); the in-place kinds read and write a.f_out.
+// wall's, emitting gv (diffuse_ghost_values, for column x).  MODE: addressing
+// (see the file comment); the in-place kinds read and write a.f_out.
 template <int PREC, bool EDGE, bool DIFFUSE, int MODE>
 __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool store,
-                                          const double (*ratio)[3][7]) {
+                                          const double (*gv)[3][Q]) {
     using E = typename Elt<PREC>::T;
     constexpr bool two = MODE == M_PULL;
     const size_t N = (size_t)a.lx * (size_t)a.lz;   // moments_out is [4][Lx][Lz]
@@ -163,12 +196,10 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
         if (!EDGE) return fin[pidx(sl, xs, z - dz, a.lx)];
         const int zs = zq - EZ[l];   // pull source row: beyond a wall -> ghost site
         if (diffuse) {
-            if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
-                const int side = zs < 0 ? 0 : 1, i = zs < 0 ? -zs - 1 : zs - a.lz;
-                const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) * ratio[side][i][3 - EX[l]];
-                return (E)(PREC == P_F64 ? f : f - W[l]);
-            }
-            return fin[pidx(sl, xs, zq - dz, a.lx)];
+            // the in-range candidate only (a clamped row); the ghost values
+            // are selected after all 37 loads have been issued
+            const int zr = zq - dz;
+            return fin[pidx(sl, xs, zr < 0 ? 0 : (zr >= a.lz ? a.lz - 1 : zr), a.lx)];
         }
         if (periodic) return fin[pidx(sl, xs, wrap(zq - dz, a.lz), a.lx)];
         if (zs < 0) return ghost[(-zs - 1) * Q + l];
@@ -204,14 +235,7 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 auto src = [&](int zz) -> E { return fin[pidx(l, xs, zz, a.lx)]; };
                 const int zs = zq - EZ[l];
                 if (diffuse) {
-                    if (zs < 0 || zs >= a.lz) {   // ghost site (x - e_lx, zs)
-                        const int side = zs < 0 ? 0 : 1, i = zs < 0 ? -zs - 1 : zs - a.lz;
-                        const double f = full_value<PREC>(ghost[(side * 3 + i) * Q + l], l) *
-                                         ratio[side][i][3 - EX[l]];
-                        v[l] = (E)(PREC == P_F64 ? f : f - W[l]);
-                    } else {
-                        v[l] = src(zs);
-                    }
+                    v[l] = src(zs < 0 ? 0 : (zs >= a.lz ? a.lz - 1 : zs));   // selected below
                 } else if (periodic) {
                     v[l] = src(wrap(zs, a.lz));
                 } else if (zs < 0) {
@@ -223,6 +247,12 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 }
             }
         }
+    }
+    if (diffuse) {
+        // ghost sites: one select per population once every load is in flight
+        // (a select next to each load made the loads wait for each other)
+#pragma unroll
+        for (int l = 0; l < Q; ++l) v[l] = diffuse_source<PREC>(v[l], gv, l, zq - EZ[l], a.lz);
     }
     auto val = [&](int l) -> E { return v[l]; };
 
@@ -394,25 +424,26 @@ static_assert(StepShape<P_F64>::BS * StepShape<P_F64>::ZT == TILE &&
                   StepShape<P_F32_DEV>::BS * StepShape<P_F32_DEV>::ZT == TILE,
               "a block of the two-buffer step covers exactly one tile (the interior path's addressing)");
 
-// Diffuse-wall rows of one column per wavefront (two-buffer step).  Lanes
-// 0..41 evaluate M/S of the 2 x 3 x 7 ghost sites the column pulls from, then
-// lane j < min(Lz, 6) steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every
-// row when Lz < 6).
+// Diffuse-wall rows of one column per wavefront (two-buffer step): the
+// column's ghost values (diffuse_ghost_values), then lane j < min(Lz, 6)
+// steps wall row j (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row when Lz < 6).
 template <int PREC, int BS>
 __device__ __forceinline__ void wall_block(const StepArgs &a, uint32_t b) {
     using E = typename Elt<PREC>::T;
     constexpr int NW = BS / 64;   // columns per block
     __shared__ double ratio[NW][2][3][7];
+    __shared__ double gv[NW][2][3][Q];
     const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
     const int x = __builtin_amdgcn_readfirstlane((int)b * NW + w);
     const bool live = x < a.lx;
-    if (live)
-        diffuse_wall_ratios<PREC>(a, static_cast<const E *>(a.f_in), static_cast<const E *>(a.ghost), x, lane,
-                                  ratio[w]);
+    const E *fin = static_cast<const E *>(a.f_in), *ghost = static_cast<const E *>(a.ghost);
+    if (live) diffuse_ghost_values<PREC>(a, fin, ghost, nullptr, x, lane, 0, ratio[w], gv[w]);
+    __syncthreads();
+    if (live) diffuse_ghost_values<PREC>(a, fin, ghost, nullptr, x, lane, 1, ratio[w], gv[w]);
     __syncthreads();
     const int nw = a.lz < 6 ? a.lz : 6;
     if (live && lane < nw)
-        step_site<PREC, true, true, M_PULL>(a, x, lane < 3 ? lane : a.lz - (nw - lane), true, ratio[w]);
+        step_site<PREC, true, true, M_PULL>(a, x, lane < 3 ? lane : a.lz - (nw - lane), true, gv[w]);
 }
 
 // One launch per step.  With diffuse walls the first nwall blocks step the
@@ -468,22 +499,24 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_inplace_kernel(StepA
 // diffuse wall's M/S from a.ratio (wall_ratio_kernel).
 template <int PREC, int MODE, bool DIFFUSE>
 __global__ __launch_bounds__(256) void step_wall_kernel(StepArgs a) {
+    using E = typename Elt<PREC>::T;
     constexpr int NW = 4;   // columns per block
     __shared__ double ratio[NW][2][3][7];
+    __shared__ double gv[NW][2][3][Q];
     const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
     const int x = __builtin_amdgcn_readfirstlane((int)blockIdx.x * NW + w);
     const bool live = x < a.lx;
     if (DIFFUSE) {
-        if (live && lane < 42) {
-            const int side = lane / 21, i = (lane % 21) / 7, dx = lane % 7 - 3;
-            ratio[w][side][i][dx + 3] = a.ratio[(size_t)(side * 3 + i) * a.lx + wrap(x + dx, a.lx)];
-        }
+        const E *ghost = static_cast<const E *>(a.ghost);
+        if (live) diffuse_ghost_values<PREC>(a, static_cast<const E *>(nullptr), ghost, a.ratio, x, lane, 0, ratio[w], gv[w]);
+        __syncthreads();
+        if (live) diffuse_ghost_values<PREC>(a, static_cast<const E *>(nullptr), ghost, a.ratio, x, lane, 1, ratio[w], gv[w]);
         __syncthreads();
     }
     const int nw = a.lz < 7 ? a.lz : 6;
     if (live && lane < nw)
         step_site<PREC, true, DIFFUSE, MODE>(a, x, lane < 3 || a.lz < 7 ? lane : a.lz - (nw - lane), true,
-                                             DIFFUSE ? ratio[w] : nullptr);
+                                             DIFFUSE ? gv[w] : nullptr);
 }
 
 // In-place kinds with diffuse walls: M/S of every ghost site into a.ratio
@@ -498,12 +531,13 @@ __global__ __launch_bounds__(256) void wall_ratio_kernel(StepArgs a) {
                                    row % 3, xg);
 }
 
-// One block (8 wavefronts, 2 per SIMD) per CU at a time.  The kernel needs
-// 126 (FP64) / 80 (FP32) VGPRs, which would let 2 / 3 blocks share a CU;
-// those ran 3.3 % / 4.5 % slower at 4096 x 12288 on MI355X (more tiles in
-// flight at once contend for DRAM banks), so each launch requests this much
+// One block (8 wavefronts, 2 per SIMD) per CU at a time.  The tile path
+// needs 126 (FP64) / 80 (FP32) VGPRs (the kernel 160 / 112 with the diffuse
+// wall rows), which would let 2 / 3 blocks share a CU; those ran 3.3 % /
+// 4.5 % slower at 4096 x 12288 on MI355X (more tiles in flight at once
+// contend for DRAM banks), so each launch requests this much
 // dynamic LDS, which the kernel never touches, to keep a second block off
-// the CU: with the kernel's static array of wall ratios (2.6 KB) a block
+// the CU: with the kernel's static arrays of the diffuse wall (17 KB) a block
 // takes more than half of the CU's 160 KB.
 constexpr size_t STEP_OCCUPANCY_LDS = 80 * 1024;
 

@@ -54,9 +54,8 @@ class RolloutConfig:
     wall: str = "dirichlet"        # or "diffuse" (LBM_WALL_DIFFUSE)
     mom_precision: str = "f64"     # "f32": stored moments in float (LBM_MOM_F32)
     # "gather" (lbm_adjoint_collide, lbm_adjoint_gather), "push" (lbm_adjoint_step)
-    # or "auto": gather with float adjoint buffers, push with double ones (the
-    # faster form of each on MI355X: 2048 x 6144 all-float 0.70-0.71 ms gather
-    # vs 0.82 ms push; 512 x 1536 double 0.110 ms vs 0.103 ms)
+    # or "auto" (= gather, the faster form on MI355X: 2048 x 6144 all-float
+    # 0.693 ms vs 0.82 ms push; 512 x 1536 double 0.082 ms vs 0.103 ms)
     adjoint_form: str = "auto"
 
     @classmethod
@@ -133,10 +132,7 @@ class Rollout:
             self.segbuf = torch.empty((self.ckpt_every, 4, c.lx, c.lz), dtype=mdtype, device=self.device)
         if c.adjoint_form not in ("gather", "push", "auto"):
             raise ValueError(f"unknown adjoint form {c.adjoint_form!r}")
-        if c.adjoint_form == "auto":
-            self.form = "gather" if c.adj_precision == "f32" else "push"
-        else:
-            self.form = c.adjoint_form
+        self.form = "gather" if c.adjoint_form == "auto" else c.adjoint_form
         p = self.params
         self.params_stream = abi.make_params(c.lx, c.lz, c.tau, c.g, p.precision, p.flags | abi.NO_COLLIDE)
         self.ckpt = {}
