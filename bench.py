@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-placement", action="store_true",
+                    help="time the lattice's first allocation instead of the fastest of several")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain copy of known size (for the HBM counters)")
     ap.add_argument("--adjoint-counter-run", action="store_true",
@@ -427,6 +429,7 @@ def main():
 
     abi.load()
     lat = Lattice.from_workload(wl)
+    placement = None if args.no_placement else lat.tune_placement()
     secs, wall = time_steps(lat, args.steps, args.warmup)
     lat.sums()                                       # raises on a diverged state
     sites = wl.lx * wl.lz
@@ -452,6 +455,10 @@ def main():
                      "traffic": traffic, "bytes_per_launch": bpl,
                      "kernel": "lbm::step_kernel", "wall_s": round(wall, 3)},
     }
+    if placement is not None:
+        # ms per step of each allocation tried before the timed steps (the
+        # first is the lattice's own); the timed steps run on the fastest
+        out["placement_trials_ms"] = placement
     if windows is not None:
         out["fused_vs_streaming"] = windows
     if not args.no_secondary and wl.precision == "f64":
@@ -467,7 +474,10 @@ def main():
                 continue
             n2 = args.steps + (args.steps % 2 if w2.inplace else 0)
             lat = Lattice.from_workload(w2)
+            pl2 = None if args.no_placement else lat.tune_placement()
             s2, _ = time_steps(lat, n2, args.warmup + (args.warmup % 2 if w2.inplace else 0))
+            if pl2 is not None:
+                sec[f"{key}_placement_trials_ms"] = pl2
             if key == "f32dev":
                 out["fused_vs_streaming_f32dev"] = interleaved_windows(lat)
             lat.sums()

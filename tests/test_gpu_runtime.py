@@ -43,3 +43,31 @@ def test_nonfinite_state_is_reported():
         lat.sums()
     s = lat.sums(check=False).cpu().numpy()
     assert not np.isfinite(s).all()
+
+
+@pytest.mark.parametrize("inplace,wall", [(False, "dirichlet"), (True, "diffuse")])
+def test_tune_placement_keeps_the_run(inplace, wall):
+    """Re-allocating the buffers for speed changes nothing of the run: the
+    state after tuning is the state before it, bit for bit, and the steps
+    after it give what an untuned lattice gives (also with an odd number of
+    in-place steps done, i.e. the single buffer in its streamed form)."""
+    from paper_1405_1253_amd.runtime import Lattice
+    from paper_1405_1253_amd import abi
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    flags = abi.wall_flag(wall)
+    lats = []
+    for _ in range(2):
+        lat = Lattice(24, 1100, wl.tau, 1e-4, flags=flags, inplace=inplace)
+        lat.init_rt3(wl.t_d, wl.t_m, wl.t_u, wl.width, m.k, m.phase, m.amp)
+        lat.step(3)
+        lats.append(lat)
+    raw = lats[0].buf[lats[0].cur].clone()
+    times = lats[0].tune_placement(trials=3, steps=4)
+    assert times is not None and len(times) == 3 and all(t > 0 for t in times)
+    assert lats[0].steps_done == 3
+    assert torch.equal(lats[0].buf[lats[0].cur].view(torch.uint8), raw.view(torch.uint8))
+    for lat in lats:
+        lat.step(5)
+    a, b = (l.state_soa().cpu().numpy() for l in lats)
+    assert np.array_equal(a, b)
