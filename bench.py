@@ -16,8 +16,10 @@ Also: the fused step against streaming alone on the same buffers, in
 interleaved windows; the same lattice in FP32 deviation storage, with the
 diffuse (mass-conserving) walls and on a single buffer, both precisions;
 streaming alone in pull and in push form; the adjoint rollouts' cost
-relative to a plain forward and the adjoint step's bandwidth (gather form
-with float adjoint buffers, push form with double ones).
+relative to a plain forward and the adjoint step's bandwidth (gather form,
+the push form's time beside it).  Before the timed steps each lattice keeps
+the fastest of a few allocations of its buffers (Lattice.tune_placement,
+every trial reported; --no-placement times the first).
 """
 import argparse
 import hashlib
