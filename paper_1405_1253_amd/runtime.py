@@ -98,7 +98,7 @@ class Lattice:
         self.steps_done += n
 
     # ---- placement ----------------------------------------------------------
-    def tune_placement(self, trials=6, steps=12):
+    def tune_placement(self, trials=12, steps=12):
         """Re-allocate the population buffers and keep the allocation on
         which the step runs fastest.
 
