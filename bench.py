@@ -278,8 +278,7 @@ def adjoint_ratio(name, budget_bytes=None, warm=True):
 
     t_push = adj_time(lambda i: abi.lbm_adjoint_step(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2]))
     t_adj = (t_push if r.form == "push" else
-             adj_time(lambda i: abi.lbm_adjoint_gather(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2],
-                                                       r.scratch)))
+             adj_time(lambda i: abi.lbm_adjoint_gather(r.params, r.ghost, mom, r.lam[i % 2], r.lam[1 - i % 2])))
     site_bytes = 2 * abi.Q * r.lam[0].element_size() + 4 * mom.element_size()
     adj_gbs = site_bytes * wl.lx * wl.lz / t_adj / 1e9
     out = {"workload": name, "steps": wl.steps, "plain_forward_s": [round(t, 4) for t in t_plain],

@@ -74,7 +74,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 4u
+#define LBM_ABI_VERSION 5u
 #define LBM_Q 37
 #define LBM_MAX_MODES 32 /* interface modes per front accepted by lbm_init_rt3 */
 #define LBM_TILE 512     /* rows per tile of a population buffer (see Layout)   */
@@ -252,8 +252,7 @@ int lbm_unpack(const lbm_params *params, const void *tiled, void *soa, int elt_b
 /*
  * lbm_scratch_bytes -- size of the scratch buffer that lbm_moments,
  * lbm_profiles, lbm_objective, lbm_init_rt3_vjp and (with diffuse walls)
- * lbm_step_inplace and lbm_adjoint_gather need (bytes).  Returns 0 for
- * invalid params.
+ * lbm_step_inplace need (bytes).  Returns 0 for invalid params.
  */
 size_t lbm_scratch_bytes(const lbm_params *params);
 
@@ -410,16 +409,15 @@ int lbm_adjoint_step(const lbm_params *params, const void *ghost, const double *
  *   mu, mu_out  (device) same type, must not overlap the inputs
  *   ghost    (device) the forward step's wall table; required with
  *            LBM_WALL_DIFFUSE, otherwise unused
- *   scratch  (device) with LBM_WALL_DIFFUSE: at least lbm_scratch_bytes
- *            bytes, overwritten (the ghost sites' sums); otherwise unused
- * Arithmetic and precision as for lbm_adjoint_step.
- * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_ESCRATCH, LBM_EVERSION,
- * LBM_EHIP.
+ * Arithmetic and precision as for lbm_adjoint_step.  Allocates nothing and
+ * needs no scratch: with LBM_WALL_DIFFUSE the blocks at the walls form the
+ * ghost sites' sums themselves.
+ * Errors: LBM_EINVAL, LBM_EALIAS, LBM_EALIGN, LBM_EVERSION, LBM_EHIP.
  */
 int lbm_adjoint_collide(const lbm_params *params, const double *moments, const void *lam, void *mu,
                         lbm_stream_t stream);
 int lbm_adjoint_gather(const lbm_params *params, const void *ghost, const double *moments, const void *mu_in,
-                       void *mu_out, void *scratch, size_t scratch_bytes, lbm_stream_t stream);
+                       void *mu_out, lbm_stream_t stream);
 
 /*
  * lbm_init_rt3_vjp -- gradient of lbm_init_rt3 with respect to the mode

@@ -20,7 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 Q = 37
 MAX_MODES = 32
 TILE = 512   # rows per tile of a population buffer (tiled layout, include/lbm.h)
@@ -94,7 +94,7 @@ def load():
                                       ctypes.c_double, _VP, _VP, _VP, ctypes.c_size_t, _VP]
         lib.lbm_adjoint_step.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
         lib.lbm_adjoint_collide.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP]
-        lib.lbm_adjoint_gather.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+        lib.lbm_adjoint_gather.argtypes = [P(lbm_params), _VP, _VP, _VP, _VP, _VP]
         lib.lbm_init_rt3_vjp.argtypes = [P(lbm_params), P(lbm_rt3_desc), _VP, _VP, _VP, _VP,
                                          ctypes.c_size_t, _VP]
         lib.lbm_profiles.argtypes = [P(lbm_params), _VP, _VP, _VP, ctypes.c_size_t, _VP]
@@ -382,7 +382,7 @@ def lbm_adjoint_collide(params, moments, lam, mu, stream=None):
     _check(st, "lbm_adjoint_collide")
 
 
-def lbm_adjoint_gather(params, ghost, moments, mu_in, mu_out, scratch=None, stream=None):
+def lbm_adjoint_gather(params, ghost, moments, mu_in, mu_out, stream=None):
     """mu_out = C^T S^T mu_in (S^T alone with NO_COLLIDE), the gather form of
     the adjoint step (see include/lbm.h)."""
     _need("ghost", ghost, _state_dtype(params), 2 * 3 * Q)
@@ -390,7 +390,7 @@ def lbm_adjoint_gather(params, ghost, moments, mu_in, mu_out, scratch=None, stre
     _need("mu_in", mu_in, _lam_dtype(params), population_elems(params))
     _need("mu_out", mu_out, _lam_dtype(params), population_elems(params))
     st = load().lbm_adjoint_gather(ctypes.byref(params), _ptr(ghost), _ptr(moments), _ptr(mu_in), _ptr(mu_out),
-                                   _ptr(scratch), _nbytes(scratch), _stream(stream))
+                                   _stream(stream))
     _check(st, "lbm_adjoint_gather")
 
 

@@ -392,18 +392,59 @@ hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s) {
 // pull/push comparison).
 //
 // Walls: where y + e_l lies beyond a wall, (S^T mu)_l(y) is 0 for the
-// Dirichlet wall and, for the diffuse wall, the ghost site s = y + e_l's sum
+// Dirichlet wall and, for the diffuse wall, the sum A(s) of the ghost site
+// s = y + e_l, formed by the blocks at the walls themselves.
+constexpr int GATHER_BS = 256;   // rows per gather block (launch shapes measured below)
+static_assert(TILE % GATHER_BS == 0, "a gather block's rows must lie in one tile");
+
+// Diffuse wall: the ghost site s = (xg, row k) emits c_m M(s) into
+// population m, so (S^T mu) at every population that streamed into s is
 // A(s) = sum_m c_m mu_m(s + e_m) / sum_m c_m over the m pointing back into
-// the lattice (c_m = its table row), formed beforehand by adjoint_gather_wall.
+// the lattice (c_m = its table row; row = side * 3 + i).  Every load is
+// issued from a clamped row and masked, so that they are in flight together.
+
+template <typename L, typename GT>
+__device__ __forceinline__ double ghost_site_sum(const AdjointArgs &a, const L *mu, int row, int xg) {
+    const int k = row < 3 ? -1 - row : a.lz + (row - 3);
+    const GT *gh = static_cast<const GT *>(a.ghost) + (size_t)row * Q;
+    constexpr bool dev = std::is_same<GT, float>::value;   // FP32 table stores f - w
+    double S = 0.0, A = 0.0;
+#pragma unroll
+    for (int m = 1; m < Q; ++m) {
+        const int zd = k + EZ[m];   // s emits population m to (xg + e_mx, zd)
+        const bool in = zd >= 0 && zd < a.lz;
+        const double c = (double)gh[m] + (dev ? W[m] : 0.0);
+        const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
+        const double v = (double)mu[pidx(m, xd, zd < 0 ? 0 : (zd >= a.lz ? a.lz - 1 : zd), a.lx)];
+        S += in ? c : 0.0;
+        A += in ? c * v : 0.0;
+    }
+    return A / S;
+}
+
 // WALL (tiles at a wall or the lattice end only): 0 Dirichlet walls, 1
-// diffuse walls, 2 periodic in z, fixed at compile time so that the gather's
-// loads sit in no branch.
+// diffuse walls with a double wall table, 3 with a float (deviation) table,
+// 2 periodic in z, fixed at compile time so that the gather's loads sit in
+// no branch.  With diffuse walls the block first forms the sums A(s) of the
+// 2 x 3 x 7 ghost sites its column gathers from (ghost_site_sum), one lane
+// each, into LDS.
 template <bool EDGE, bool SHIFT, typename L, typename MT, int WALL = 0>
 __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x, int z0) {
     using A = AdjAcc<L, MT>;
     const L *__restrict__ in = static_cast<const L *>(a.lam_in);
     L *__restrict__ out = static_cast<L *>(a.lam_out);
     const int z = z0 + (int)threadIdx.x;
+    constexpr bool diffuse = WALL == 1 || WALL == 3;
+    __shared__ double gsum[6][7];   // [side * 3 + i][dx + 3]: A of ghost site (x + dx, row i of side)
+    if (diffuse) {
+        const int t = (int)threadIdx.x, row = t / 7;
+        if (t < 42 && (row < 3 ? z0 < 3 : z0 + GATHER_BS + 3 > a.lz)) {   // the walls this block reaches
+            const int xg = wrap(x + t % 7 - 3, a.lx);
+            gsum[row][t % 7] = WALL == 3 ? ghost_site_sum<L, float>(a, in, row, xg)
+                                         : ghost_site_sum<L, double>(a, in, row, xg);
+        }
+        __syncthreads();   // every lane of the block reaches this (the return below comes after)
+    }
     if (EDGE && z >= a.lz) return;
     const int zt = z0 / TILE, zl = z % TILE;
     const long long tstep = (long long)a.lx * (Q * TILE) - TILE;
@@ -438,9 +479,9 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
         const L *tb = in + ((size_t)zt * (size_t)a.lx + (size_t)xs) * (Q * TILE);
         const L inval = tb[tile_off(l, zl + (zc - z), tstep)];
         L ghostval = L(0);
-        if (WALL == 1) {   // ghost site (x + e_lx, zs)
+        if (diffuse) {   // ghost site (x + e_lx, zs)
             const int row = zs < 0 ? -zs - 1 : (zs >= a.lz ? 3 + zs - a.lz : 0);
-            ghostval = (L)a.wall_a[(size_t)row * (size_t)a.lx + (size_t)xs];
+            ghostval = (L)gsum[row][EX[l] + 3];
         }
         lam[l] = (zs >= 0 && zs < a.lz) ? inval : ghostval;
     }
@@ -451,15 +492,14 @@ __device__ __forceinline__ void adjoint_gather_tile(const AdjointArgs &a, int x,
 
 // Launch shape of the gather form: 256 rows per block (a tile holds two
 // such blocks); 4 wavefronts per SIMD with float buffers and float moments
-// (128 VGPRs, no spills), 2 otherwise.  Measured on MI355X, 2048 x 6144
+// (128 VGPRs, no spills in the interior tiles), 2 otherwise.  Measured on
+// MI355X, 2048 x 6144
 // all-float: 0.704 ms, against 0.718 with 512-row blocks at 3 wavefronts
 // per SIMD, 0.726 with 256 rows and the moments loaded after the gathers,
 // 0.737 with non-temporal gathers and 0.724 with XCD-contiguous tile order;
 // 512 x 1536 double: 0.110 ms with 256 rows vs 0.145 with 512.  With the
 // wall tiles' loads free of per-lane branches (above): 0.693 ms and
 // 0.082 ms.
-constexpr int GATHER_BS = 256;
-static_assert(TILE % GATHER_BS == 0, "a gather block's rows must lie in one tile");
 template <typename L, typename MT>
 struct GatherWaves {
     static constexpr int value = (sizeof(L) == 4 && sizeof(MT) == 4) ? 4 : 2;
@@ -471,43 +511,20 @@ void adjoint_gather_kernel(AdjointArgs a, int nzb) {
     const int x = (int)(blockIdx.x / (uint32_t)nzb);
     const int z0 = (int)(blockIdx.x % (uint32_t)nzb) * BS;
     const bool edge = SHIFT ? (z0 < 3) || (z0 + BS + 3 > a.lz) : (z0 + BS > a.lz);
-    if (!edge)
+    // the interior tiles are the hot path: marked as such, register allocation
+    // places the spills that 128 VGPRs force (all-float) in the wall tiles
+    if (__builtin_expect(!edge, 1))
         adjoint_gather_tile<false, SHIFT, L, MT>(a, x, z0);
     else if (!SHIFT)
         adjoint_gather_tile<true, false, L, MT>(a, x, z0);
     else if (a.flags & F_PERIODIC_Z)
         adjoint_gather_tile<true, true, L, MT, 2>(a, x, z0);
+    else if ((a.flags & F_WALL_DIFFUSE) && a.precision == P_F32_DEV)
+        adjoint_gather_tile<true, true, L, MT, 3>(a, x, z0);
     else if (a.flags & F_WALL_DIFFUSE)
         adjoint_gather_tile<true, true, L, MT, 1>(a, x, z0);
     else
         adjoint_gather_tile<true, true, L, MT, 0>(a, x, z0);
-}
-
-// Diffuse wall, gather form: A(s) of every ghost site s = (xg, row) into
-// a.wall_a [2 x 3][Lx] from the input mu, before the gather step reads it.
-template <typename L, typename GT>
-__global__ __launch_bounds__(BLOCK) void adjoint_gather_wall(AdjointArgs a) {
-    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t >= 6 * a.lx) return;
-    const L *__restrict__ mu = static_cast<const L *>(a.lam_in);
-    const int xg = t % a.lx, row = t / a.lx;      // row = side * 3 + i
-    const int k = row < 3 ? -1 - row : a.lz + (row - 3);
-    const GT *gh = static_cast<const GT *>(a.ghost) + (size_t)row * Q;
-    constexpr bool dev = std::is_same<GT, float>::value;   // FP32 table stores f - w
-    double S = 0.0, A = 0.0;
-#pragma unroll
-    for (int m = 1; m < Q; ++m) {
-        // the ghost site emits population m to (xg + e_mx, zd); loads from a
-        // clamped row, masked, so that they are all in flight at once
-        const int zd = k + EZ[m];
-        const bool in = zd >= 0 && zd < a.lz;
-        const double c = (double)gh[m] + (dev ? W[m] : 0.0);
-        const int xd = EX[m] == 0 ? xg : wrap(xg + EX[m], a.lx);
-        const double v = (double)mu[pidx(m, xd, zd < 0 ? 0 : (zd >= a.lz ? a.lz - 1 : zd), a.lx)];
-        S += in ? c : 0.0;
-        A += in ? c * v : 0.0;
-    }
-    a.wall_a[t] = A / S;
 }
 
 template <typename L, typename MT>
@@ -524,18 +541,6 @@ static void launch_gather_t(const AdjointArgs &a, bool shift, hipStream_t s) {
 hipError_t launch_adjoint_gather(const AdjointArgs &a, bool shift, hipStream_t s) {
     const bool f32 = (a.flags & F_ADJ_F32) != 0;
     const bool m32 = (a.flags & F_MOM_F32) != 0;
-    if (shift && (a.flags & F_WALL_DIFFUSE) && !(a.flags & F_PERIODIC_Z)) {
-        const dim3 wgrid((uint32_t)((6 * a.lx + BLOCK - 1) / BLOCK));
-        const bool gf = a.precision == P_F32_DEV;
-        if (f32 && gf)
-            hipLaunchKernelGGL((adjoint_gather_wall<float, float>), wgrid, dim3(BLOCK), 0, s, a);
-        else if (f32)
-            hipLaunchKernelGGL((adjoint_gather_wall<float, double>), wgrid, dim3(BLOCK), 0, s, a);
-        else if (gf)
-            hipLaunchKernelGGL((adjoint_gather_wall<double, float>), wgrid, dim3(BLOCK), 0, s, a);
-        else
-            hipLaunchKernelGGL((adjoint_gather_wall<double, double>), wgrid, dim3(BLOCK), 0, s, a);
-    }
     if (f32 && m32)
         launch_gather_t<float, float>(a, shift, s);
     else if (f32)

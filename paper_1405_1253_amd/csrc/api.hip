@@ -479,7 +479,6 @@ int lbm_adjoint_step(const lbm_params *p, const void *ghost, const double *momen
     a.omega = 1.0 / p->tau;
     a.g = p->g;
     a.flags = p->flags;
-    a.wall_a = nullptr;
     return hip_status(lbm::launch_adjoint_step(a, (hipStream_t)stream));
 }
 
@@ -505,28 +504,21 @@ int lbm_adjoint_collide(const lbm_params *p, const double *moments, const void *
     a.omega = 1.0 / p->tau;
     a.g = p->g;
     a.flags = p->flags;
-    a.wall_a = nullptr;
     return hip_status(lbm::launch_adjoint_gather(a, false, (hipStream_t)stream));
 }
 
 int lbm_adjoint_gather(const lbm_params *p, const void *ghost, const double *moments, const void *mu_in,
-                       void *mu_out, void *scratch, size_t scratch_bytes, lbm_stream_t stream) {
+                       void *mu_out, lbm_stream_t stream) {
     bool empty = false;
     int st = check_params(p, &empty);
     if (st != LBM_OK) return st;
     if (!mu_in || !mu_out || (!moments && !(p->flags & LBM_NO_COLLIDE))) return LBM_EINVAL;
-    const bool diffuse = (p->flags & LBM_WALL_DIFFUSE) != 0;
-    if (!ghost && diffuse) return LBM_EINVAL;
-    if (!aligned(mu_in, 16) || !aligned(mu_out, 16) || !aligned(moments, 16) || !aligned(ghost, 8) ||
-        !aligned(scratch, 8))
+    if (!ghost && (p->flags & LBM_WALL_DIFFUSE)) return LBM_EINVAL;
+    if (!aligned(mu_in, 16) || !aligned(mu_out, 16) || !aligned(moments, 16) || !aligned(ghost, 8))
         return LBM_EALIGN;
     if (empty) return LBM_OK;
-    const size_t rb = wall_ratio_bytes(p->lx);
-    if (diffuse && (!scratch || scratch_bytes < rb)) return LBM_ESCRATCH;
     const size_t lb = lam_bytes(p), mb = mom_bytes(p), gb = ghost_bytes(p);
-    if (overlap(mu_in, lb, mu_out, lb) || overlap(moments, mb, mu_out, lb) || overlap(ghost, gb, mu_out, lb) ||
-        (diffuse && (overlap(scratch, rb, mu_in, lb) || overlap(scratch, rb, mu_out, lb) ||
-                     overlap(scratch, rb, moments, mb) || overlap(scratch, rb, ghost, gb))))
+    if (overlap(mu_in, lb, mu_out, lb) || overlap(moments, mb, mu_out, lb) || overlap(ghost, gb, mu_out, lb))
         return LBM_EALIAS;
     lbm::AdjointArgs a;
     a.mom = moments;
@@ -540,7 +532,6 @@ int lbm_adjoint_gather(const lbm_params *p, const void *ghost, const double *mom
     a.omega = 1.0 / p->tau;
     a.g = p->g;
     a.flags = p->flags;
-    a.wall_a = diffuse ? static_cast<double *>(scratch) : nullptr;
     return hip_status(lbm::launch_adjoint_gather(a, true, (hipStream_t)stream));
 }
 

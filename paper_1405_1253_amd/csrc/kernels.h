@@ -71,7 +71,6 @@ struct AdjointArgs {
     int lx, lz;
     double tau, omega, g;
     uint32_t flags;
-    double *wall_a;        // gather form with F_WALL_DIFFUSE: scratch [2 x 3][lx], the ghost sites' sums
 };
 hipError_t launch_adjoint_step(const AdjointArgs &a, hipStream_t s);
 // Gather form: shift = false: lam_out = C^T lam_in (the collision alone, per

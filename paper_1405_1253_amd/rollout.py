@@ -196,12 +196,11 @@ class Rollout:
                 abi.lbm_adjoint_collide(self.params, mom, src, dst)
             else:
                 # mu_t = C_t^T S^T mu_{t+1}
-                abi.lbm_adjoint_gather(self.params, self.ghost, mom, src, dst, self.scratch)
+                abi.lbm_adjoint_gather(self.params, self.ghost, mom, src, dst)
             li = 1 - li
         if self.form == "gather" and c.nsteps > 0:
             # lam_0 = S^T mu_1
-            abi.lbm_adjoint_gather(self.params_stream, self.ghost, None, self.lam[li], self.lam[1 - li],
-                                   self.scratch)
+            abi.lbm_adjoint_gather(self.params_stream, self.ghost, None, self.lam[li], self.lam[1 - li])
             li = 1 - li
         d_amp = torch.empty_like(self.amp)
         abi.lbm_init_rt3_vjp(self.params, self.desc, self.amp, self.lam[li], d_amp, self.scratch)

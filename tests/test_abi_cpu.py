@@ -133,7 +133,7 @@ def test_every_entry_point_accepts_an_empty_lattice(abi):
                 "objective": lib.lbm_objective(r, ctypes.byref(desc.c), a, 1.0, 1.0, b, None, c, 0, None),
                 "adjoint_step": lib.lbm_adjoint_step(r, a, b, c, d, None),
                 "adjoint_collide": lib.lbm_adjoint_collide(r, b, c, d, None),
-                "adjoint_gather": lib.lbm_adjoint_gather(r, a, b, c, d, e, 0, None),
+                "adjoint_gather": lib.lbm_adjoint_gather(r, a, b, c, d, None),
                 "init_rt3_vjp": lib.lbm_init_rt3_vjp(r, ctypes.byref(desc.c), a, b, c, d, 0, None),
             }
             assert all(v == 0 for v in calls.values()), (lx, lz, flags, calls)

@@ -73,20 +73,19 @@ def test_collide_and_gather_parity(abi, lx, lz, mode):
     rng = np.random.default_rng(lx + 3 * lz)
     lam = rng.standard_normal((37, lx, lz))
     mu = rng.standard_normal((37, lx, lz))
-    scratch = torch.empty(max(abi.lbm_scratch_bytes(params), 256), dtype=torch.uint8, device=DEV)
     # C^T alone
     out = abi.empty_populations(params, torch.float64)
     abi.lbm_adjoint_collide(params, mom, abi.to_tiled(params, lam), out)
     e_c = _rel_max(abi.to_soa(params, out).cpu().numpy(), A.collide_vjp(lam, g, p))
     # S^T alone (NO_COLLIDE)
     p_nc = abi.make_params(lx, lz, p.tau, p.g, flags=flags | abi.NO_COLLIDE)
-    abi.lbm_adjoint_gather(p_nc, _t(ghost), None, abi.to_tiled(params, mu), out, scratch)
+    abi.lbm_adjoint_gather(p_nc, _t(ghost), None, abi.to_tiled(params, mu), out)
     st = A.pull_transpose(mu, p, ghost)
     got_s = abi.to_soa(params, out).cpu().numpy()
     inner = slice(3, max(lz - 3, 3))
     e_s = _rel_max(got_s, st)
     # C^T S^T
-    abi.lbm_adjoint_gather(params, _t(ghost), mom, abi.to_tiled(params, mu), out, scratch)
+    abi.lbm_adjoint_gather(params, _t(ghost), mom, abi.to_tiled(params, mu), out)
     e_cs = _rel_max(abi.to_soa(params, out).cpu().numpy(), A.collide_vjp(st, g, p))
     print(f"{mode} {lx}x{lz}: C^T {e_c:.2e}, S^T {e_s:.2e}, C^T S^T {e_cs:.2e}")
     assert e_c <= 1e-12 and e_cs <= 1e-12
@@ -108,9 +107,8 @@ def test_gather_float_forms(abi, lx, lz, mode, form):
     g = O.pull(f, ghost, p)
     mu = np.random.default_rng(5 * lx + lz).standard_normal((37, lx, lz)).astype(np.float32)
     want = A.collide_vjp(A.pull_transpose(mu.astype(np.float64), p, ghost), g, p)
-    scratch = torch.empty(max(abi.lbm_scratch_bytes(params), 256), dtype=torch.uint8, device=DEV)
     out = abi.empty_populations(params, torch.float32)
-    abi.lbm_adjoint_gather(params, _t(ghost), mom, abi.to_tiled(params, mu), out, scratch)
+    abi.lbm_adjoint_gather(params, _t(ghost), mom, abi.to_tiled(params, mu), out)
     got = abi.to_soa(params, out).cpu().numpy().astype(np.float64)
     err = _rel_max(got, want)
     if form == "float_buffers":

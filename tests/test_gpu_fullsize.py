@@ -126,8 +126,7 @@ def test_fullsize_adjoint_step_sampled_columns(name, form):
     lam = torch.randn(f.shape, dtype=sdt, device="cuda", generator=gen)
     out = torch.empty_like(f)
     if f32:
-        scratch = torch.empty(max(abi.lbm_scratch_bytes(p_adj), 256), dtype=torch.uint8, device="cuda")
-        abi.lbm_adjoint_gather(p_adj, gh, mom, lam, out, scratch)
+        abi.lbm_adjoint_gather(p_adj, gh, mom, lam, out)
     else:
         abi.lbm_adjoint_step(p_adj, gh, mom, lam, out)
     w = abi.lbm_lattice()[1] if f32 else np.zeros(abi.Q)
