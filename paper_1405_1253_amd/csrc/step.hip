@@ -46,8 +46,8 @@
 // ghost site s is the sum of A[m][s - e_m] over the m leaving the lattice.
 // Launches of an in-place step: (diffuse walls) wall_ratio_kernel saves M/S
 // of every ghost site before those slots are overwritten; step_inplace_kernel
-// steps rows 3..Lz-4 with the interior code only; step_wall_kernel steps the
-// six wall rows per column.  Keeping the wall rows' parking and ghost
+// steps the six wall rows per column in its leading blocks and rows
+// 3..Lz-4 with the interior code only in the others.  Keeping the wall rows' parking and ghost
 // substitution out of the tile kernel keeps it free of spills (184-186
 // VGPRs in FP64, 132-162 in FP32, instead of 256 with spills).
 #include "common.h"
@@ -474,16 +474,52 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_kernel(StepArgs a, i
     }
 }
 
-// In-place kinds, rows 3 .. Lz-4 (every source and destination inside the
-// walls): only the branch-free interior code, which keeps the kernel's
-// register count at the two-buffer level; in tiles that reach a wall the
-// lanes outside these rows load a valid row and store nothing.  The wall rows
-// are stepped by step_wall_kernel.
-template <int PREC, int MODE>
-__global__ __launch_bounds__(StepShape<PREC>::BS) void step_inplace_kernel(StepArgs a, int nzb) {
+// In-place kinds: the wall rows (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row
+// when Lz < 7) of BS/64 columns, one wavefront per column, with the
+// Dirichlet table or the diffuse wall's M/S from a.ratio (wall_ratio_kernel).
+template <int PREC, int MODE, bool DIFFUSE, int BS>
+__device__ __forceinline__ void inplace_wall_block(const StepArgs &a, uint32_t b) {
+    using E = typename Elt<PREC>::T;
+    constexpr int NW = BS / 64;   // columns per block
+    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    const int x = __builtin_amdgcn_readfirstlane((int)b * NW + w);
+    const bool live = x < a.lx;
+    const double(*gvw)[3][Q] = nullptr;
+    if constexpr (DIFFUSE) {
+        __shared__ double ratio[NW][2][3][7];
+        __shared__ double gv[NW][2][3][Q];
+        const E *ghost = static_cast<const E *>(a.ghost);
+        if (live) diffuse_ghost_values<PREC>(a, static_cast<const E *>(nullptr), ghost, a.ratio, x, lane, 0, ratio[w], gv[w]);
+        __syncthreads();
+        if (live) diffuse_ghost_values<PREC>(a, static_cast<const E *>(nullptr), ghost, a.ratio, x, lane, 1, ratio[w], gv[w]);
+        __syncthreads();
+        gvw = gv[w];
+    }
+    const int nw = a.lz < 7 ? a.lz : 6;
+    if (live && lane < nw)
+        step_site<PREC, true, DIFFUSE, MODE>(a, x, lane < 3 || a.lz < 7 ? lane : a.lz - (nw - lane), true, gvw);
+}
+
+// In-place kinds: the first nwall blocks step the wall rows
+// (inplace_wall_block; WALLS = 1 Dirichlet, 2 diffuse; no wall code with
+// WALLS = 0), the others rows 3 .. Lz-4 of one tile each (every source and
+// destination inside the walls) with only the branch-free interior code,
+// which keeps the tile path's register count at the two-buffer level; in
+// tiles that reach a wall the lanes outside these rows load a valid row and
+// store nothing.  Wall and tile blocks may run at the same time: every site
+// reads and writes only its own 37 slots.
+template <int PREC, int MODE, int WALLS>
+__global__ __launch_bounds__(StepShape<PREC>::BS) void step_inplace_kernel(StepArgs a, int nzb, uint32_t nwall) {
     constexpr int BS = StepShape<PREC>::BS, ZT = StepShape<PREC>::ZT;
-    const int x = (int)(blockIdx.x / (uint32_t)nzb);
-    const int zt = (int)(blockIdx.x % (uint32_t)nzb) * ZT;
+    if constexpr (WALLS != 0) {
+        if (__builtin_expect(blockIdx.x < nwall, 0)) {
+            inplace_wall_block<PREC, MODE, WALLS == 2, BS>(a, blockIdx.x);
+            return;
+        }
+    }
+    const uint32_t t = blockIdx.x - nwall;
+    const int x = (int)(t / (uint32_t)nzb);
+    const int zt = (int)(t % (uint32_t)nzb) * ZT;
     for (int k = 0; k < ZT; ++k) {
         const int z0 = (zt + k) * BS;
         if (z0 >= a.lz) break;
@@ -492,31 +528,6 @@ __global__ __launch_bounds__(StepShape<PREC>::BS) void step_inplace_kernel(StepA
         const int zc = z < 3 ? 3 : (z > a.lz - 4 ? a.lz - 4 : z);
         step_site<PREC, false, false, MODE>(a, x, zc, inner, nullptr);
     }
-}
-
-// In-place kinds: the wall rows (rows 0, 1, 2, Lz-3, Lz-2, Lz-1; every row
-// when Lz < 7), one wavefront per column, with the Dirichlet table or the
-// diffuse wall's M/S from a.ratio (wall_ratio_kernel).
-template <int PREC, int MODE, bool DIFFUSE>
-__global__ __launch_bounds__(256) void step_wall_kernel(StepArgs a) {
-    using E = typename Elt<PREC>::T;
-    constexpr int NW = 4;   // columns per block
-    __shared__ double ratio[NW][2][3][7];
-    __shared__ double gv[NW][2][3][Q];
-    const int w = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
-    const int x = __builtin_amdgcn_readfirstlane((int)blockIdx.x * NW + w);
-    const bool live = x < a.lx;
-    if (DIFFUSE) {
-        const E *ghost = static_cast<const E *>(a.ghost);
-        if (live) diffuse_ghost_values<PREC>(a, static_cast<const E *>(nullptr), ghost, a.ratio, x, lane, 0, ratio[w], gv[w]);
-        __syncthreads();
-        if (live) diffuse_ghost_values<PREC>(a, static_cast<const E *>(nullptr), ghost, a.ratio, x, lane, 1, ratio[w], gv[w]);
-        __syncthreads();
-    }
-    const int nw = a.lz < 7 ? a.lz : 6;
-    if (live && lane < nw)
-        step_site<PREC, true, DIFFUSE, MODE>(a, x, lane < 3 || a.lz < 7 ? lane : a.lz - (nw - lane), true,
-                                             DIFFUSE ? gv[w] : nullptr);
 }
 
 // In-place kinds with diffuse walls: M/S of every ghost site into a.ratio
@@ -551,22 +562,33 @@ static void launch_prec(const StepArgs &a, hipStream_t s) {
                        nwall);
 }
 
+// One launch (wall blocks first, then tiles) removes the wall rows' own
+// launch and its latency: measured on MI355X, 512 x 1536 in-place steps
+// 0.071 ms against 0.085 (FP64) and 0.041 against 0.056 (FP32), 4096 x
+// 12288 FP32 2.99-3.00 ms against 3.01-3.03.  Large FP64 lattices keep two
+// launches: with the wall code in it the tile kernel ran 1.2-1.9 % slower at
+// 2048 x 6144 and 4096 x 12288 (also when launched for the tiles alone), so
+// there a kernel without wall code steps the tiles and the combined kernel,
+// launched for its wall blocks only, the wall rows.
+constexpr long long INPLACE_SPLIT_SITES_F64 = 1ll << 22;
+
 template <int PREC, int MODE>
 static void launch_inplace(const StepArgs &a, hipStream_t s) {
     constexpr int BS = StepShape<PREC>::BS, span = BS * StepShape<PREC>::ZT;
     const bool diffuse = (a.flags & F_WALL_DIFFUSE) != 0;
     if (diffuse)
         hipLaunchKernelGGL(wall_ratio_kernel<PREC>, dim3((uint32_t)((6 * a.lx + 255) / 256)), dim3(256), 0, s, a);
-    if (a.lz >= 7) {
-        const int nzb = (a.lz + span - 1) / span;
-        hipLaunchKernelGGL((step_inplace_kernel<PREC, MODE>), dim3((uint32_t)nzb * (uint32_t)a.lx), dim3(BS), 0, s,
-                           a, nzb);
+    const int nzb = (a.lz + span - 1) / span;
+    const uint32_t nwall = (uint32_t)((a.lx + BS / 64 - 1) / (BS / 64));
+    uint32_t ntile = a.lz >= 7 ? (uint32_t)nzb * (uint32_t)a.lx : 0u;
+    if (PREC == P_F64 && ntile != 0 && (long long)a.lx * a.lz >= INPLACE_SPLIT_SITES_F64) {
+        hipLaunchKernelGGL((step_inplace_kernel<PREC, MODE, 0>), dim3(ntile), dim3(BS), 0, s, a, nzb, 0u);
+        ntile = 0;
     }
-    const dim3 wgrid((uint32_t)((a.lx + 3) / 4));
     if (diffuse)
-        hipLaunchKernelGGL((step_wall_kernel<PREC, MODE, true>), wgrid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((step_inplace_kernel<PREC, MODE, 2>), dim3(nwall + ntile), dim3(BS), 0, s, a, nzb, nwall);
     else
-        hipLaunchKernelGGL((step_wall_kernel<PREC, MODE, false>), wgrid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((step_inplace_kernel<PREC, MODE, 1>), dim3(nwall + ntile), dim3(BS), 0, s, a, nzb, nwall);
 }
 
 hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s) {

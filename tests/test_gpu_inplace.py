@@ -131,6 +131,28 @@ def test_in_place_equals_two_buffers(abi, prec, wall):
         assert merr <= (1e-13 if prec == "f64" else 1e-6), (steps, merr)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32dev"])
+@pytest.mark.parametrize("wall", ["dirichlet", "diffuse"])
+@pytest.mark.parametrize("lx,lz", [(3, 6), (2, 3), (100, 5), (5, 7), (16, 2051), (1024, 4100)])
+def test_in_place_equals_two_buffers_tiny_and_ragged(abi, prec, wall, lx, lz):
+    """Lattices whose rows are all wall rows (Lz < 7), the smallest with an
+    interior row, a ragged one of several tiles (wall blocks and tile blocks
+    in one launch) and a ragged FP64 one of 2^22 sites or more (tiles and
+    wall rows in two launches): 4 steps against the two-buffer step, same
+    bars."""
+    params = abi.make_params(lx, lz, 0.6, 3e-4, abi.F64 if prec == "f64" else abi.F32_DEV, abi.wall_flag(wall))
+    _, f0, gh = _init(abi, params, 11, width=1.0 if lz < 64 else 4.0, nmodes=2)
+    a, _ = _in_place(abi, params, gh, f0, 4)
+    b, _ = _two_buffer(abi, params, gh, f0, 4)
+    a, b = abi.to_soa(params, a).double(), abi.to_soa(params, b).double()
+    if prec == "f64":
+        err, bar = float(((a - b).abs() / b.abs()).max()), 1e-13
+    else:
+        err, bar = float((a - b).abs().max() / b.abs().max()), 2.0 ** -20
+    print(f"{prec} {wall} {lx}x{lz}: in place vs two buffers {err:.2e}")
+    assert torch.isfinite(a).all() and err <= bar
+
+
 def test_in_place_parity_with_oracle_ragged_and_tiny(abi):
     for lx, lz, steps, width, wall in ((37, 300, 12, 4.0, "dirichlet"), (37, 300, 12, 4.0, "diffuse"),
                                        (2, 3, 4, 1.0, "diffuse"), (4, 6, 4, 1.0, "dirichlet"),
