@@ -84,17 +84,22 @@ def main(argv=None):
                     help="RT times at which to record the row profiles")
     ap.add_argument("--seed", type=int, default=None,
                     help="seed of the interface modes (default: the workload's); one realisation per seed")
+    ap.add_argument("--precision", choices=("f64", "f32dev"), default=None,
+                    help="population storage (default: the workload's; the paper's runs are double precision)")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     from . import abi
     wl = WORKLOADS[args.workload]
     if args.seed is not None:
         wl = dataclasses.replace(wl, seed=args.seed)
+    if args.precision is not None:
+        wl = dataclasses.replace(wl, precision=args.precision)
     tau = rt_time(wl, abi.lbm_lattice()[0])
     nsteps = int(round(args.tau_rt * tau / args.every)) * args.every
     ptimes = [int(round(float(x) * tau / args.every)) * args.every for x in args.profiles_at.split(",")]
     ptimes = [p for p in ptimes if p <= nsteps]
-    print(json.dumps({"workload": wl.name, "seed": wl.seed, "tau_rt_steps": tau, "nsteps": nsteps}), flush=True)
+    print(json.dumps({"workload": wl.name, "seed": wl.seed, "precision": wl.precision, "tau_rt_steps": tau,
+                      "nsteps": nsteps}), flush=True)
 
     def progress(t, L, s):
         print(f"step {t} (t/tau {t / tau:.2f}): L_tot {L:.1f}, {s:.0f} s", flush=True)
