@@ -2,6 +2,7 @@
 
     python -m paper_1405_1253_amd.precision fields   [--steps 20000]
     python -m paper_1405_1253_amd.precision gradient [--steps 5000]
+    python -m paper_1405_1253_amd.precision interface [--steps 20000]
 
 fields:   the 4096 x 12288 three-layer workload is run in FP64 and in FP32
           deviation storage for the same number of steps; the renormalised
@@ -11,6 +12,11 @@ fields:   the 4096 x 12288 three-layer workload is run in FP64 and in FP32
           KE of both runs are printed.
 gradient: dJ/d amp of the 2048 x 6144 rollout with FP32 storage and float
           adjoint buffers against the same rollout in FP64 throughout.
+interface: the double-front workload of the paper's runs (Sec. IV, 6144
+          rows, 64 columns) with flat interfaces (zero amplitudes: the
+          fronts only diffuse, every column alike) at tau = 0.50546 (the
+          paper's), 0.52 and 0.7: L_u + L_d in FP32 deviation storage over
+          FP64 after 2,000 steps and after the given number.
 Each mode prints one JSON line.  All arithmetic runs in the library's kernels;
 differences are reduced on the device with torch.
 """
@@ -88,13 +94,41 @@ def gradient(steps):
             "seconds": time.perf_counter() - t0}
 
 
+def interface(steps):
+    import dataclasses
+    import numpy as np
+    from .runtime import Lattice
+    from .workload import WORKLOADS, draw_modes
+    base = WORKLOADS["rt3_2400x6144_paper"]
+    m = draw_modes(base.seed)
+    res = {"mode": "interface", "workload": base.name, "lx": 64, "steps": [0, 2000, steps], "L_tot": {}}
+    t0 = time.perf_counter()
+    for tau in (base.tau, 0.52, 0.7):
+        row = {}
+        for prec in ("f64", "f32dev"):
+            lat = Lattice.from_workload(dataclasses.replace(base, lx=64, tau=tau, precision=prec), modes=m,
+                                        amp=np.zeros_like(m.amp))
+            vals, done = [float(lat.objective()[2])], 0
+            for n in (2000, steps):
+                lat.step(n - done)
+                done = n
+                vals.append(float(lat.objective()[2]))
+            row[prec] = vals
+        row["f32_over_f64"] = [b / a for a, b in zip(row["f64"], row["f32dev"])]
+        res["L_tot"][f"tau={tau}"] = row
+    res["seconds"] = time.perf_counter() - t0
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=("fields", "gradient"))
+    ap.add_argument("mode", choices=("fields", "gradient", "interface"))
     ap.add_argument("--steps", type=int, default=None)
     a = ap.parse_args(argv)
     if a.mode == "fields":
         out = fields(a.steps or 20000)
+    elif a.mode == "interface":
+        out = interface(a.steps or 20000)
     else:
         out = gradient(a.steps or 5000)
     print(json.dumps(out), flush=True)
