@@ -103,8 +103,14 @@ enum lbm_flags {
                             in lbm_adjoint_step with LBM_MOM_F32 as well            */
     LBM_WALL_DIFFUSE = 8u, /* mass-conserving diffuse walls instead of Dirichlet walls
                             (lbm_step); not with LBM_PERIODIC_Z                       */
-    LBM_MOM_F32 = 16u     /* the step's moments_out and the adjoint's moments are float
+    LBM_MOM_F32 = 16u,    /* the step's moments_out and the adjoint's moments are float
                             [4][Lx][Lz] (half the memory of stored adjoint moments)   */
+    LBM_COLLIDE_F64 = 32u /* LBM_F32_DEV steps: equilibrium and relaxation in double,
+                            one rounding to float per stored value (ignored in FP64).
+                            Near tau = 1/2 the float collision biases the interface
+                            diffusion (mixing lengths +2 % after 20,000 steps at
+                            tau = 0.50546); this removes it at 2-3 % of the
+                            two-buffer step's time                                   */
 };
 
 typedef struct lbm_params {

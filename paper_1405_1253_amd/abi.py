@@ -25,7 +25,7 @@ Q = 37
 MAX_MODES = 32
 TILE = 512   # rows per tile of a population buffer (tiled layout, include/lbm.h)
 F64, F32_DEV = 0, 1
-PERIODIC_Z, NO_COLLIDE, ADJ_F32, WALL_DIFFUSE, MOM_F32 = 1, 2, 4, 8, 16
+PERIODIC_Z, NO_COLLIDE, ADJ_F32, WALL_DIFFUSE, MOM_F32, COLLIDE_F64 = 1, 2, 4, 8, 16, 32
 INPLACE_FROM_STATE, INPLACE_FROM_STREAMED = 0, 1
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_EALIAS", -3: "LBM_EALIGN",

@@ -33,11 +33,11 @@ def alpha_tot(t, L, atwood, g):
         return np.where(L > 0, Ld * Ld / (4.0 * atwood * g * L), np.nan)
 
 
-def run(wl, nsteps, every, profile_times=(), progress=None):
+def run(wl, nsteps, every, profile_times=(), progress=None, flags=0):
     import torch
     from . import abi
     from .runtime import Lattice
-    lat = Lattice.from_workload(wl)
+    lat = Lattice.from_workload(wl, flags=flags)
     t_rec, L_rec, Lu_rec, Ld_rec, ke_rec, prof = [], [], [], [], [], {}
     want = sorted(set(int(x) for x in profile_times))
     t = 0
@@ -86,6 +86,8 @@ def main(argv=None):
                     help="seed of the interface modes (default: the workload's); one realisation per seed")
     ap.add_argument("--precision", choices=("f64", "f32dev"), default=None,
                     help="population storage (default: the workload's; the paper's runs are double precision)")
+    ap.add_argument("--collide-f64", action="store_true",
+                    help="with f32dev storage: the collision in double arithmetic (LBM_COLLIDE_F64)")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     from . import abi
@@ -98,13 +100,13 @@ def main(argv=None):
     nsteps = int(round(args.tau_rt * tau / args.every)) * args.every
     ptimes = [int(round(float(x) * tau / args.every)) * args.every for x in args.profiles_at.split(",")]
     ptimes = [p for p in ptimes if p <= nsteps]
-    print(json.dumps({"workload": wl.name, "seed": wl.seed, "precision": wl.precision, "tau_rt_steps": tau,
-                      "nsteps": nsteps}), flush=True)
+    print(json.dumps({"workload": wl.name, "seed": wl.seed, "precision": wl.precision,
+                      "collide_f64": bool(args.collide_f64), "tau_rt_steps": tau, "nsteps": nsteps}), flush=True)
 
     def progress(t, L, s):
         print(f"step {t} (t/tau {t / tau:.2f}): L_tot {L:.1f}, {s:.0f} s", flush=True)
 
-    out = run(wl, nsteps, args.every, ptimes, progress)
+    out = run(wl, nsteps, args.every, ptimes, progress, flags=abi.COLLIDE_F64 if args.collide_f64 else 0)
     out["alpha_tot"] = alpha_tot(out["t"], out["L_tot"], out["atwood"], out["g"])
     np.savez(args.out, **out)
     print(json.dumps({"done": True, "seconds": out["seconds"], "steps": nsteps}), flush=True)

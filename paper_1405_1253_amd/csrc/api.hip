@@ -11,6 +11,11 @@
 #include "common.h"
 #include "kernels.h"
 
+static_assert(lbm::F_PERIODIC_Z == LBM_PERIODIC_Z && lbm::F_NO_COLLIDE == LBM_NO_COLLIDE &&
+                  lbm::F_ADJ_F32 == LBM_ADJ_F32 && lbm::F_WALL_DIFFUSE == LBM_WALL_DIFFUSE &&
+                  lbm::F_MOM_F32 == LBM_MOM_F32 && lbm::F_COLLIDE_F64 == LBM_COLLIDE_F64,
+              "the kernels read params->flags as given");
+
 // Scratch of the allocation-free diagnostics entry point (lbm_moments_noalloc).
 static __device__ __align__(256) unsigned char scratch[LBM_STATIC_SCRATCH_BYTES];
 
@@ -37,7 +42,8 @@ int check_params(const lbm_params *p, bool *empty) {
     if (p->lx < 0 || p->lz < 0) return LBM_EINVAL;
     if ((long long)p->lx * (long long)p->lz > MAX_SITES) return LBM_EINVAL;
     if (p->precision != LBM_F64 && p->precision != LBM_F32_DEV) return LBM_EINVAL;
-    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32 | LBM_WALL_DIFFUSE | LBM_MOM_F32))
+    if (p->flags & ~(uint32_t)(LBM_PERIODIC_Z | LBM_NO_COLLIDE | LBM_ADJ_F32 | LBM_WALL_DIFFUSE | LBM_MOM_F32 |
+                            LBM_COLLIDE_F64))
         return LBM_EINVAL;
     if ((p->flags & LBM_PERIODIC_Z) && (p->flags & LBM_WALL_DIFFUSE)) return LBM_EINVAL;
     if (p->reserved != 0) return LBM_EINVAL;

@@ -8,8 +8,12 @@
 
 namespace lbm {
 
-enum : uint32_t { F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u, F_WALL_DIFFUSE = 8u, F_MOM_F32 = 16u };
-enum : int { P_F64 = 0, P_F32_DEV = 1 };
+enum : uint32_t {
+    F_PERIODIC_Z = 1u, F_NO_COLLIDE = 2u, F_ADJ_F32 = 4u, F_WALL_DIFFUSE = 8u, F_MOM_F32 = 16u, F_COLLIDE_F64 = 32u
+};
+// P_F32_DEV_C64: float deviation storage as P_F32_DEV, collision arithmetic in
+// double (F_COLLIDE_F64); a kernel template value only, never a params value.
+enum : int { P_F64 = 0, P_F32_DEV = 1, P_F32_DEV_C64 = 2 };
 
 struct StepArgs {
     const void *f_in;    // two-buffer step: input state (unused in place)

@@ -65,6 +65,10 @@ template <>
 struct Elt<P_F32_DEV> {
     using T = float;
 };
+template <>
+struct Elt<P_F32_DEV_C64> {
+    using T = float;
+};
 
 // Addressing of a step: two buffers (pull), or one of the two in-place kinds.
 enum : int { M_PULL = 0, M_IN_O = 1, M_IN_E = 2 };
@@ -369,6 +373,33 @@ __device__ __forceinline__ void step_site(const StepArgs &a, int x, int z, bool 
                 }
             }
         }
+    } else if (PREC == P_F32_DEV_C64) {
+        // deviation form in double arithmetic, one rounding to float per
+        // stored value: d^eq_l = w_l (drho + rho (P_l - 1))
+        const double om = a.omega;
+#pragma unroll
+        for (int s = 0; s < NSHELL; ++s) {
+            const ShellCoef<double> c = shell_coef<double>(u2, th, XI2_SHELL[s]);
+            const double w = W_SHELL[s];
+#pragma unroll
+            for (int l = 0; l < Q; ++l) {
+                if (SHELL[l] != s) continue;
+                if (l == 0) {
+                    const double v0 = (double)val(0);
+                    if (active) put(0, (E)(v0 + om * (w * (s0 + rho * c.a0m1) - v0)));
+                    continue;
+                }
+                if ((l & 1) == 0) continue;
+                double ev, od;
+                pair_poly<double>(c, R * (EX[l] * vx + EZ[l] * vz), ev, od);
+                const double dp = w * (s0 + rho * (ev + od)), dm = w * (s0 + rho * (ev - od));
+                const double vp = (double)val(l), vm = (double)val(l + 1);
+                if (active) {
+                    put(l, (E)(vp + om * (dp - vp)));
+                    put(l + 1, (E)(vm + om * (dm - vm)));
+                }
+            }
+        }
     } else {
         // deviation form: d^eq_l = w_l (rho P_l - 1) = w_l (drho + rho (P_l - 1))
         const float drho = (float)s0, rhof = (float)rho;
@@ -420,8 +451,13 @@ template <>
 struct StepShape<P_F32_DEV> {
     static constexpr int BS = TILE, ZT = 1;
 };
+template <>
+struct StepShape<P_F32_DEV_C64> {
+    static constexpr int BS = TILE, ZT = 1;
+};
 static_assert(StepShape<P_F64>::BS * StepShape<P_F64>::ZT == TILE &&
-                  StepShape<P_F32_DEV>::BS * StepShape<P_F32_DEV>::ZT == TILE,
+                  StepShape<P_F32_DEV>::BS * StepShape<P_F32_DEV>::ZT == TILE &&
+                  StepShape<P_F32_DEV_C64>::BS * StepShape<P_F32_DEV_C64>::ZT == TILE,
               "a block of the two-buffer step covers exactly one tile (the interior path's addressing)");
 
 // Diffuse-wall rows of one column per wavefront (two-buffer step): the
@@ -594,6 +630,8 @@ static void launch_inplace(const StepArgs &a, hipStream_t s) {
 hipError_t launch_step(const StepArgs &a, int precision, hipStream_t s) {
     if (precision == P_F64)
         launch_prec<P_F64>(a, s);
+    else if (a.flags & F_COLLIDE_F64)
+        launch_prec<P_F32_DEV_C64>(a, s);
     else
         launch_prec<P_F32_DEV>(a, s);
     return hipGetLastError();
@@ -605,6 +643,11 @@ hipError_t launch_step_inplace(const StepArgs &a, int precision, int kind, hipSt
             launch_inplace<P_F64, M_IN_O>(a, s);
         else
             launch_inplace<P_F64, M_IN_E>(a, s);
+    } else if (a.flags & F_COLLIDE_F64) {
+        if (kind == 0)
+            launch_inplace<P_F32_DEV_C64, M_IN_O>(a, s);
+        else
+            launch_inplace<P_F32_DEV_C64, M_IN_E>(a, s);
     } else {
         if (kind == 0)
             launch_inplace<P_F32_DEV, M_IN_O>(a, s);

@@ -15,8 +15,9 @@ gradient: dJ/d amp of the 2048 x 6144 rollout with FP32 storage and float
 interface: the double-front workload of the paper's runs (Sec. IV, 6144
           rows, 64 columns) with flat interfaces (zero amplitudes: the
           fronts only diffuse, every column alike) at tau = 0.50546 (the
-          paper's), 0.52 and 0.7: L_u + L_d in FP32 deviation storage over
-          FP64 after 2,000 steps and after the given number.
+          paper's), 0.52 and 0.7: L_u + L_d in FP32 deviation storage (float
+          collision, and double collision with LBM_COLLIDE_F64) over FP64
+          after 2,000 steps and after the given number.
 Each mode prints one JSON line.  All arithmetic runs in the library's kernels;
 differences are reduced on the device with torch.
 """
@@ -103,18 +104,21 @@ def interface(steps):
     m = draw_modes(base.seed)
     res = {"mode": "interface", "workload": base.name, "lx": 64, "steps": [0, 2000, steps], "L_tot": {}}
     t0 = time.perf_counter()
+    from . import abi
     for tau in (base.tau, 0.52, 0.7):
         row = {}
-        for prec in ("f64", "f32dev"):
+        for key, prec, flags in (("f64", "f64", 0), ("f32dev", "f32dev", 0),
+                                 ("f32dev_collide_f64", "f32dev", abi.COLLIDE_F64)):
             lat = Lattice.from_workload(dataclasses.replace(base, lx=64, tau=tau, precision=prec), modes=m,
-                                        amp=np.zeros_like(m.amp))
+                                        amp=np.zeros_like(m.amp), flags=flags)
             vals, done = [float(lat.objective()[2])], 0
             for n in (2000, steps):
                 lat.step(n - done)
                 done = n
                 vals.append(float(lat.objective()[2]))
-            row[prec] = vals
+            row[key] = vals
         row["f32_over_f64"] = [b / a for a, b in zip(row["f64"], row["f32dev"])]
+        row["f32_collide_f64_over_f64"] = [b / a for a, b in zip(row["f64"], row["f32dev_collide_f64"])]
         res["L_tot"][f"tau={tau}"] = row
     res["seconds"] = time.perf_counter() - t0
     return res

@@ -65,7 +65,7 @@ def test_step_rejects_bad_arguments(abi):
     assert _call_step(abi, mk(-1, 16, 0.7, 0.0)) == -1
     assert _call_step(abi, mk(1 << 15, 1 << 15, 0.7, 0.0)) == -1  # too many sites
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, precision=7)) == -1
-    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=32)) == -1          # unknown flag
+    assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=64)) == -1          # unknown flag
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=abi.PERIODIC_Z | abi.WALL_DIFFUSE)) == -1
     assert _call_step(abi, mk(16, 16, 0.7, 0.0, flags=abi.WALL_DIFFUSE), ghost=None) == -1
     p = mk(16, 16, 0.7, 0.0)
@@ -232,7 +232,7 @@ def test_binding_constants_match_the_header():
     h = header_constants()
     assert h["LBM_ABI_VERSION"] == mod.ABI_VERSION and h["LBM_Q"] == mod.Q
     assert h["LBM_MAX_MODES"] == mod.MAX_MODES and h["LBM_TILE"] == mod.TILE
-    for name in ("F64", "F32_DEV", "PERIODIC_Z", "NO_COLLIDE", "ADJ_F32", "WALL_DIFFUSE", "MOM_F32",
+    for name in ("F64", "F32_DEV", "PERIODIC_Z", "NO_COLLIDE", "ADJ_F32", "WALL_DIFFUSE", "MOM_F32", "COLLIDE_F64",
                  "INPLACE_FROM_STATE", "INPLACE_FROM_STREAMED"):
         assert h["LBM_" + name] == getattr(mod, name), name
     status = {v: k for k, v in h.items() if k in ("LBM_OK",) or (k.startswith("LBM_E") and v < 0)}

@@ -131,7 +131,7 @@ def test_in_place_equals_two_buffers(abi, prec, wall):
         assert merr <= (1e-13 if prec == "f64" else 1e-6), (steps, merr)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32dev"])
+@pytest.mark.parametrize("prec", ["f64", "f32dev", "f32dev_collide_f64"])
 @pytest.mark.parametrize("wall", ["dirichlet", "diffuse"])
 @pytest.mark.parametrize("lx,lz", [(3, 6), (2, 3), (100, 5), (5, 7), (16, 2051), (1024, 4100)])
 def test_in_place_equals_two_buffers_tiny_and_ragged(abi, prec, wall, lx, lz):
@@ -140,7 +140,8 @@ def test_in_place_equals_two_buffers_tiny_and_ragged(abi, prec, wall, lx, lz):
     in one launch) and a ragged FP64 one of 2^22 sites or more (tiles and
     wall rows in two launches): 4 steps against the two-buffer step, same
     bars."""
-    params = abi.make_params(lx, lz, 0.6, 3e-4, abi.F64 if prec == "f64" else abi.F32_DEV, abi.wall_flag(wall))
+    params = abi.make_params(lx, lz, 0.6, 3e-4, abi.F64 if prec == "f64" else abi.F32_DEV,
+                             abi.wall_flag(wall) | (abi.COLLIDE_F64 if prec == "f32dev_collide_f64" else 0))
     _, f0, gh = _init(abi, params, 11, width=1.0 if lz < 64 else 4.0, nmodes=2)
     a, _ = _in_place(abi, params, gh, f0, 4)
     b, _ = _two_buffer(abi, params, gh, f0, 4)
