@@ -37,7 +37,9 @@
  * the plain layout [37][Lx][Lz] (z fastest).  Element type by precision:
  *    LBM_F64      double, the population f_l itself;
  *    LBM_F32_DEV  float, the deviation f_l - w_l from the rest state of unit
- *                 density (w_l = quadrature weight).
+ *                 density (w_l = quadrature weight); the step forms the
+ *                 moments in double and the equilibrium and relaxation in
+ *                 float (in double with LBM_COLLIDE_F64).
  * Field buffers ([4][Lx][Lz], [Lz]) are always double, in the plain layout;
  * so are the step's moments ([4][Lx][Lz]).
  *
