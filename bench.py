@@ -13,8 +13,9 @@ stream the kernel runs on, plus the HBM bytes of the committed counter
 summary while it matches the kernel code) and the CPU oracle timed on the
 host cores (one process per core, each on its own strip of the lattice).
 Also: the fused step against streaming alone on the same buffers, in
-interleaved windows; the same lattice in FP32 deviation storage, with the
-diffuse (mass-conserving) walls and on a single buffer, both precisions;
+interleaved windows; the same lattice in FP32 deviation storage (also with
+the collision in double, LBM_COLLIDE_F64), with the diffuse
+(mass-conserving) walls and on a single buffer, both precisions;
 streaming alone in pull and in push form; the adjoint rollouts' cost
 relative to a plain forward and the adjoint step's bandwidth (gather form,
 the push form's time beside it).  Before the timed steps each lattice keeps
@@ -463,18 +464,19 @@ def main():
     if windows is not None:
         out["fused_vs_streaming"] = windows
     if not args.no_secondary and wl.precision == "f64":
-        # the same lattice in FP32 deviation storage, both precisions with the
+        # the same lattice in FP32 deviation storage (float collision, and
+        # double collision with LBM_COLLIDE_F64), both precisions with the
         # diffuse (mass-conserving) wall rule, and both on a single buffer
         # (in-place steps come in pairs: step counts rounded up to even)
         sec = {}
-        for suffix, key in (("_f32", "f32dev"), ("_diffuse", "diffuse_f64"),
-                            ("_f32_diffuse", "diffuse_f32dev"), ("_inplace", "inplace_f64"),
-                            ("_f32_inplace", "inplace_f32dev")):
+        for suffix, key, flags in (("_f32", "f32dev", 0), ("_f32", "f32dev_collide_f64", abi.COLLIDE_F64),
+                                   ("_diffuse", "diffuse_f64", 0), ("_f32_diffuse", "diffuse_f32dev", 0),
+                                   ("_inplace", "inplace_f64", 0), ("_f32_inplace", "inplace_f32dev", 0)):
             w2 = WORKLOADS.get(wl.name + suffix)
             if w2 is None:
                 continue
             n2 = args.steps + (args.steps % 2 if w2.inplace else 0)
-            lat = Lattice.from_workload(w2)
+            lat = Lattice.from_workload(w2, flags=flags)
             pl2 = None if args.no_placement else lat.tune_placement()
             s2, _ = time_steps(lat, n2, args.warmup + (args.warmup % 2 if w2.inplace else 0))
             if pl2 is not None:
