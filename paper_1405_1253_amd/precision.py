@@ -1,6 +1,6 @@
 """FP32 deviation storage against FP64 on the same workload.
 
-    python -m paper_1405_1253_amd.precision fields   [--steps 20000]
+    python -m paper_1405_1253_amd.precision fields   [--steps 20000] [--collide-f64]
     python -m paper_1405_1253_amd.precision gradient [--steps 5000]
     python -m paper_1405_1253_amd.precision interface [--steps 20000]
 
@@ -40,13 +40,14 @@ def _field_errors(a, b):
     return out
 
 
-def fields(steps):
+def fields(steps, collide_f64=False):
+    from . import abi
     from .runtime import Lattice
     from .workload import WORKLOADS
-    res = {"mode": "fields", "steps": steps}
+    res = {"mode": "fields", "steps": steps, "collide_f64": collide_f64}
     t0 = time.perf_counter()
     lat64 = Lattice.from_workload(WORKLOADS["rt3_4096x12288"])
-    lat32 = Lattice.from_workload(WORKLOADS["rt3_4096x12288_f32"])
+    lat32 = Lattice.from_workload(WORKLOADS["rt3_4096x12288_f32"], flags=abi.COLLIDE_F64 if collide_f64 else 0)
     done = 0
     while done < steps:
         n = min(2000, steps - done)
@@ -128,9 +129,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=("fields", "gradient", "interface"))
     ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--collide-f64", action="store_true", help="fields: the FP32 run collides in double")
     a = ap.parse_args(argv)
     if a.mode == "fields":
-        out = fields(a.steps or 20000)
+        out = fields(a.steps or 20000, a.collide_f64)
     elif a.mode == "interface":
         out = interface(a.steps or 20000)
     else:
