@@ -29,3 +29,30 @@ def test_paper_workloads():
     nu = d.tau - 0.5
     ra = (d.t_d - d.t_u) * (r * d.lz) ** 3 * d.g / nu ** 2
     assert abs(ra / 1e10 - 1) < 1e-3
+
+
+def test_campaign_options_reach_the_run(tmp_path, monkeypatch):
+    """--seed, --precision and --collide-f64 change the workload and the
+    lattice flags handed to the run (the run itself is replaced here: no
+    GPU), and the series the run returns is written with alpha_tot."""
+    from paper_1405_1253_amd import abi
+    seen = {}
+
+    def fake_run(wl, nsteps, every, ptimes, progress, flags=0):
+        seen.update(wl=wl, nsteps=nsteps, flags=flags, ptimes=list(ptimes))
+        t = np.arange(0, nsteps + 1, every, dtype=float)
+        return {"t": t, "L_tot": 1.0 + t ** 2, "L_u": t, "L_d": t, "KE": t, "profile_steps": np.array([]),
+                "profiles": np.zeros((0, 4, wl.lz)), "tau_rt": 1.0, "atwood": wl.atwood, "g": wl.g,
+                "seconds": 0.0}
+
+    monkeypatch.setattr(C, "run", fake_run)
+    out = tmp_path / "run.npz"
+    C.main(["--workload", "rt3_2400x6144_paper", "--precision", "f32dev", "--collide-f64", "--seed", "1406",
+            "--tau-rt", "0.5", "--every", "2000", "--profiles-at", "0,0.25", "--out", str(out)])
+    assert seen["wl"].precision == "f32dev" and seen["wl"].seed == 1406
+    assert seen["flags"] == abi.COLLIDE_F64 and seen["nsteps"] % 2000 == 0 and seen["nsteps"] > 0
+    assert seen["ptimes"][0] == 0 and all(p % 2000 == 0 for p in seen["ptimes"])
+    C.main(["--workload", "rt2_2400x6144_paper", "--precision", "f64", "--tau-rt", "0.5", "--out", str(out)])
+    assert seen["wl"].precision == "f64" and seen["flags"] == 0
+    saved = np.load(out)
+    assert np.isfinite(saved["alpha_tot"][1:-1]).all()
