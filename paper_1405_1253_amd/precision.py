@@ -1,7 +1,7 @@
 """FP32 deviation storage against FP64 on the same workload.
 
     python -m paper_1405_1253_amd.precision fields   [--steps 20000] [--collide-f64]
-    python -m paper_1405_1253_amd.precision gradient [--steps 5000]
+    python -m paper_1405_1253_amd.precision gradient [--steps 5000] [--collide-f64]
     python -m paper_1405_1253_amd.precision interface [--steps 20000]
 
 fields:   the 4096 x 12288 three-layer workload is run in FP64 and in FP32
@@ -71,7 +71,7 @@ def fields(steps, collide_f64=False):
     return res
 
 
-def gradient(steps):
+def gradient(steps, collide_f64=False):
     from .rollout import Rollout, RolloutConfig
     from .workload import WORKLOADS, draw_modes
     wl = WORKLOADS["rt3_2048x6144_adj"]
@@ -81,7 +81,8 @@ def gradient(steps):
     t0 = time.perf_counter()
     for prec, adj in (("f32dev", "f32"), ("f64", "f64")):
         r = Rollout(RolloutConfig.from_workload(wl, m, nsteps=steps, precision=prec, adj_precision=adj,
-                                                mom_precision=adj, moment_budget_bytes=40 << 30))
+                                                mom_precision=adj, moment_budget_bytes=40 << 30,
+                                                collide_f64=collide_f64 and prec == "f32dev"))
         J = r.forward(amp)[0].item()
         grads[prec] = (J, r.backward())
         del r
@@ -89,7 +90,7 @@ def gradient(steps):
         print(f"{prec} rollout done: {time.perf_counter() - t0:.0f} s", flush=True)
     (J32, g32), (J64, g64) = grads["f32dev"], grads["f64"]
     err = (g32 - g64).abs()
-    return {"mode": "gradient", "steps": steps, "J_f64": J64, "J_f32": J32,
+    return {"mode": "gradient", "steps": steps, "collide_f64": collide_f64, "J_f64": J64, "J_f32": J32,
             "J_rel_err": abs(J32 / J64 - 1), "grad_max_abs_err": float(err.max()),
             "grad_max_err_over_max_grad": float(err.max() / g64.abs().max()),
             "grad_rms_rel_err": float((err.pow(2).mean() / g64.pow(2).mean()).sqrt()),
@@ -129,14 +130,14 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=("fields", "gradient", "interface"))
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--collide-f64", action="store_true", help="fields: the FP32 run collides in double")
+    ap.add_argument("--collide-f64", action="store_true", help="fields, gradient: the FP32 run collides in double")
     a = ap.parse_args(argv)
     if a.mode == "fields":
         out = fields(a.steps or 20000, a.collide_f64)
     elif a.mode == "interface":
         out = interface(a.steps or 20000)
     else:
-        out = gradient(a.steps or 5000)
+        out = gradient(a.steps or 5000, a.collide_f64)
     print(json.dumps(out), flush=True)
 
 

@@ -57,6 +57,7 @@ class RolloutConfig:
     # or "auto" (= gather, the faster form on MI355X: 2048 x 6144 all-float
     # 0.693 ms vs 0.82 ms push; 512 x 1536 double 0.082 ms vs 0.103 ms)
     adjoint_form: str = "auto"
+    collide_f64: bool = False      # FP32-dev forward steps collide in double (LBM_COLLIDE_F64)
 
     @classmethod
     def from_workload(cls, wl: Workload, modes, nsteps=None, **kw):
@@ -110,6 +111,7 @@ class Rollout:
                                       abi.F64 if c.precision == "f64" else abi.F32_DEV,
                                       (abi.ADJ_F32 if c.adj_precision == "f32" else 0)
                                       | (abi.MOM_F32 if c.mom_precision == "f32" else 0)
+                                      | (abi.COLLIDE_F64 if c.collide_f64 else 0)
                                       | abi.wall_flag(c.wall))
         self.ldtype = torch.float32 if c.adj_precision == "f32" else torch.float64
         self.desc = abi.RT3Desc(c.t_d, c.t_m, c.t_u, c.width, c.k, c.phase)
