@@ -136,6 +136,33 @@ def test_rollout_gradient_vs_oracle_128x384(abi, wall):
     assert np.array_equal(g2, got)
 
 
+def test_rollout_with_the_double_collision(abi):
+    """RolloutConfig(collide_f64=True) on an FP32-dev state (float adjoint
+    buffers and moments): the forward steps and the recomputed ones take the
+    same kernel, so recomputing from checkpoints gives the bitwise same
+    gradient; J lies closer to the all-FP64 rollout's than with the float
+    collision, and the gradient within the float forms' bar of 1e-3 of its
+    largest entry (128 x 384, 20 steps)."""
+    wl = W.WORKLOADS["rt3_128x384"]
+    m = W.draw_modes(wl.seed)
+    amp = torch.as_tensor(m.amp, device=DEV)
+    kw = dict(precision="f32dev", adj_precision="f32", mom_precision="f32")
+    res = {}
+    for key, extra in (("f64", dict()), ("f32", kw), ("c64", dict(kw, collide_f64=True)),
+                       ("c64_recompute", dict(kw, collide_f64=True, ckpt_every=7,
+                                              moment_budget_bytes=3 * 4 * wl.lx * wl.lz * 4))):
+        r = _rollout(wl, m, 20, **extra)
+        J = r.forward(amp)[0].item()
+        res[key] = (J, r.backward().cpu().numpy(), r.recomputed_steps)
+    (J64, g64, _), (J32, g32, _) = res["f64"], res["f32"]
+    (Jc, gc, _), (Jr, gr, nr) = res["c64"], res["c64_recompute"]
+    assert nr == 17 and Jr == Jc and np.array_equal(gr, gc)
+    e32, ec = _rel_max(g32, g64), _rel_max(gc, g64)
+    print(f"vs FP64: J {abs(J32 / J64 - 1):.2e} / {abs(Jc / J64 - 1):.2e}, gradient {e32:.2e} / {ec:.2e} "
+          "(float / double collision)")
+    assert abs(Jc / J64 - 1) <= abs(J32 / J64 - 1) and ec <= 1e-3
+
+
 @pytest.mark.parametrize("name", ["rt3_512x1536_adj", "rt3_512x1536_adj_diffuse"])
 def test_gradient_vs_finite_differences_512x1536(abi, name):
     """Central differences of the GPU forward at h = 1e-6 carry a rounding
